@@ -1,0 +1,218 @@
+/*
+ * xrdvi — C ABI of the MI355X (gfx950) hot path of variational Bayesian
+ * crystalline-phase identification from X-ray diffraction.
+ *
+ * The model (paper, Appendix A): observed counts y_i at diffraction angles
+ * x_i (2-theta, degrees) follow a Poisson law around the profile
+ *     f(x_i) = B_i + sum_k h_k sum_m I_m^(k) V(x_i; p_m^(k) + mu_k, w_k, r_k)
+ * with V the pseudo-Voigt (1-r) G + r L of a unit-area Gaussian G and a
+ * unit-area Lorentzian L sharing full width at half maximum w.  Each
+ * candidate phase k carries four latents phi_k = (h_k, mu_k, w_k, r_k):
+ * weight, shift, width and Lorentz fraction.  Priors (Sec. 2.2 and
+ * Appendix B.2): h ~ Exp(rate lambda), mu ~ N(0, mu_sd), w ~ Gamma(shape,
+ * rate), r ~ U(0,1).  The posterior is approximated by a mean-field
+ * Gaussian q (Sec. 3.2) over unconstrained z with h = exp(z_h), mu = z_mu,
+ * w = exp(z_w), r = logistic(z_r); its parameters are loc (means) and
+ * logscale (log standard deviations), each laid out [4][K] with rows
+ * (h, mu, w, r).
+ *
+ * Conventions for every call:
+ *  - Return value: XRDVI_OK (0) or a negative error code; a message for the
+ *    last error of the calling thread is available from xrdvi_last_error().
+ *    No exception or abort crosses this interface.
+ *  - "device" pointers are HIP device memory on the context's GPU; "host"
+ *    pointers are ordinary memory.  The caller owns every pointer it passes
+ *    and keeps device inputs valid until the work enqueued on `stream` has
+ *    completed.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls only enqueue
+ *    work on it and never synchronise unless stated.
+ *  - Arguments checked on the host before any work is enqueued fail with
+ *    XRDVI_EINVAL and leave outputs untouched.
+ *  - A context, problem or tape may be used from one thread at a time.
+ *  - A problem is used only while its context lives and a tape only while
+ *    its problem lives; the *_destroy calls themselves may run in any order.
+ */
+#ifndef XRDVI_H
+#define XRDVI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XRDVI_API __attribute__((visibility("default")))
+
+enum {
+    XRDVI_OK = 0,
+    XRDVI_PENDING = 1,
+    XRDVI_EINVAL = -1,     /* invalid argument, detected on the host        */
+    XRDVI_ENOMEM = -2,     /* device or host allocation failed / never fits */
+    XRDVI_EDEVICE = -3,    /* a HIP runtime call failed                     */
+    XRDVI_EBUSY = -4,      /* serving queue full                            */
+    XRDVI_ENOENT = -5,     /* unknown ticket                                */
+    XRDVI_ECANCELED = -6   /* request cancelled                             */
+};
+
+typedef struct xrdvi_ctx xrdvi_ctx;
+typedef struct xrdvi_problem xrdvi_problem;
+typedef struct xrdvi_tape xrdvi_tape;
+typedef struct xrdvi_server xrdvi_server;
+
+/* Prior hyper-parameters (Sec. 2.2; Appendix B.2). */
+typedef struct {
+    double lambda_h;  /* rate of the exponential prior on h; 0 selects
+                         1 / max_i(y_i - B_i), the paper's choice        */
+    double mu_sd;     /* sd of the normal prior on the shift, 0.03 deg    */
+    double w_shape;   /* gamma prior on the width: shape 3 ...            */
+    double w_rate;    /* ... and rate 100 (mean 0.03 deg)                  */
+} xrdvi_prior;
+
+/*
+ * One diffractogram and its candidate set (Appendix A.1).  HOST pointers;
+ * the library copies and validates them at xrdvi_problem_create.
+ *   x[N]        2-theta grid, finite, strictly ascending, inside (0, 180)
+ *   y[N]        observed counts, finite, >= 0 (non-integers are accepted;
+ *               ln y! is taken as lgamma(y + 1))
+ *   bg[N]       background B_i, finite, > 0 (estimated beforehand)
+ *   peak_off[K+1] CSR offsets of the ragged peak lists: peak_off[0] = 0,
+ *               non-decreasing; phase k owns peaks peak_off[k]..peak_off[k+1]-1
+ *   peak_pos[T] peak positions p_m (deg), finite; T = peak_off[K]
+ *   peak_int[T] relative intensities I_m in [0, 1]
+ *   cutoff      c >= 0: peak m of phase k contributes only at points with
+ *               rho - c w <= x_i <= rho + c w (rho = p_m + mu_k, w = FWHM);
+ *               c = 0 keeps every point (the paper's dense sum)
+ */
+typedef struct {
+    int32_t N, K;
+    const double *x, *y, *bg;
+    const int32_t *peak_off;
+    const double *peak_pos, *peak_int;
+    double cutoff;
+    xrdvi_prior prior;
+} xrdvi_problem_desc;
+
+XRDVI_API const char *xrdvi_last_error(void);
+XRDVI_API int xrdvi_version(void);
+
+/* Host-only validation of a problem description (no GPU needed).  Returns
+ * XRDVI_OK or XRDVI_EINVAL with a message. */
+XRDVI_API int xrdvi_validate(const xrdvi_problem_desc *desc);
+
+/* Context bound to one GPU (`device` index).  Owns a growable workspace for
+ * xrdvi_profile and xrdvi_window_plan. */
+XRDVI_API int xrdvi_ctx_create(int device, xrdvi_ctx **out);
+XRDVI_API int xrdvi_ctx_destroy(xrdvi_ctx *ctx);
+
+/* Validates `desc`, copies it to the device and lays it out for the kernels
+ * (peaks ordered by position inside each phase, tile-relative coordinates,
+ * ln y!).  Synchronous.  The problem must not outlive its context. */
+XRDVI_API int xrdvi_problem_create(xrdvi_ctx *ctx,
+                                   const xrdvi_problem_desc *desc,
+                                   xrdvi_problem **out);
+XRDVI_API int xrdvi_problem_destroy(xrdvi_problem *prob);
+/* Sizes and the resolved prior rate lambda_h. Any output may be NULL. */
+XRDVI_API int xrdvi_problem_info(const xrdvi_problem *prob, int32_t *N,
+                                 int32_t *K, int32_t *total_peaks,
+                                 double *lambda_h);
+
+/* Per-step device state for S samples of one problem: noise, samples,
+ * window plan and the adjoint's per-tile partial sums (never the S x K x N
+ * peak basis).  Holds the saved state between xrdvi_elbo_fwd and
+ * xrdvi_elbo_bwd. */
+XRDVI_API int xrdvi_tape_create(xrdvi_ctx *ctx, const xrdvi_problem *prob,
+                                int32_t S, xrdvi_tape **out);
+XRDVI_API int xrdvi_tape_destroy(xrdvi_tape *tape);
+
+/*
+ * Profile f[s][i] = B_i + sum_k h_k C_k(x_i) (Appendix A.2, signal and
+ * profile equations) at given constrained latents.
+ *   phi    device double [S][4][K], rows (h, mu, w, r); requires h >= 0,
+ *          w > 0, 0 <= r <= 1 (other values give unspecified output)
+ *   f_out  device float [S][N]
+ * Peak values are evaluated in FP32 on tile-relative coordinates and summed
+ * onto the FP64 background.  The first call at a larger S grows the
+ * context workspace (allocation, synchronous).
+ */
+XRDVI_API int xrdvi_profile(xrdvi_ctx *ctx, const xrdvi_problem *prob,
+                            int32_t S, const double *phi, float *f_out,
+                            void *stream);
+
+/*
+ * Window plan: for each sample s and peak m (caller's peak order),
+ * lo[s][m] = first grid index inside [rho - c w, rho + c w] and hi[s][m] =
+ * one past the last (lo = hi when empty), with rho = p_m + mu and the bounds
+ * formed in FP64 by single rounded operations.  With c = 0 every window is
+ * [0, N).
+ *   phi     device double [S][4][K]
+ *   lo, hi  device int32 [S][T]
+ */
+XRDVI_API int xrdvi_window_plan(xrdvi_ctx *ctx, const xrdvi_problem *prob,
+                                int32_t S, const double *phi, int32_t *lo,
+                                int32_t *hi, void *stream);
+
+/*
+ * ELBO forward (Sec. 3.2): draws z_s = loc + exp(logscale) * eps_s for
+ * s < S, evaluates the profile, the Poisson log-likelihood (Appendix A.2)
+ * and the estimate
+ *   L = (1/S) sum_s [ln p(Y|phi_s) + ln p(phi_s) + ln|J(z_s)|]
+ *       + sum_j logscale_j + 2K (1 + ln 2 pi).
+ *   loc, logscale  device double [4][K]
+ *   eps            device double [S][4][K] standard-normal noise, or NULL to
+ *                  draw it on the device from Philox4x32-10 keyed by
+ *                  (seed, step) with Box-Muller (counter (j/4, s, step))
+ *   need_grad      non-zero: also run the recomputing adjoint so that
+ *                  xrdvi_elbo_bwd can follow (fused forward + adjoint)
+ *   elbo_out       device double [1]
+ *   loglik_out     device double [S] (ln p(Y|phi_s)), or NULL
+ *   tape           created for this problem with the same S
+ * The tape keeps copies of eps, the samples and exp(logscale), so loc and
+ * logscale may change after the call.
+ */
+XRDVI_API int xrdvi_elbo_fwd(xrdvi_ctx *ctx, const xrdvi_problem *prob,
+                             int32_t S, const double *loc,
+                             const double *logscale, const double *eps,
+                             uint64_t seed, uint64_t step, int32_t need_grad,
+                             double *elbo_out, double *loglik_out,
+                             xrdvi_tape *tape, void *stream);
+
+/*
+ * ELBO gradient: g times dL/dloc and dL/dlogscale of the estimate computed
+ * by the last xrdvi_elbo_fwd on this tape (which must have had need_grad
+ * set; else XRDVI_EINVAL), with g = grad_scale, further multiplied by
+ * *grad_scale_dev when that device pointer is non-NULL (an upstream
+ * gradient that stays on the device).  Window edges are held fixed (the
+ * estimate is piecewise smooth in the parameters when c > 0).
+ *   grad_loc, grad_logscale  device double [4][K]
+ */
+XRDVI_API int xrdvi_elbo_bwd(xrdvi_ctx *ctx, const xrdvi_tape *tape,
+                             double grad_scale, const double *grad_scale_dev,
+                             double *grad_loc, double *grad_logscale,
+                             void *stream);
+
+/*
+ * Copies the constrained samples phi_s = T(z_s) drawn by the last
+ * xrdvi_elbo_fwd on `tape` into phi_out (device double [S][4][K]), e.g. to
+ * inspect the approximate posterior or to count the peak-points of the
+ * step with xrdvi_window_plan.
+ */
+XRDVI_API int xrdvi_tape_samples(xrdvi_ctx *ctx, const xrdvi_tape *tape,
+                                 double *phi_out, void *stream);
+
+/*
+ * Kernel timing for measurement: while enabled, every fused profile /
+ * likelihood / adjoint launch issued through `ctx` is bracketed by HIP
+ * events recorded on the launch's own stream.  xrdvi_timing_read waits for
+ * the recorded events and returns the summed kernel time (ms) and launch
+ * count; reset != 0 clears them.  Disabled by default; enabling costs two
+ * event records per launch.
+ */
+XRDVI_API int xrdvi_timing_enable(xrdvi_ctx *ctx, int32_t enable);
+XRDVI_API int xrdvi_timing_read(xrdvi_ctx *ctx, double *ms_total,
+                                int64_t *launches, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XRDVI_H */

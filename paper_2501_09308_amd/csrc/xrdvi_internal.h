@@ -1,0 +1,44 @@
+// Host-side internals shared by the C ABI, the launchers and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "xrdvi_device.h"
+
+namespace xrdvi {
+
+hipError_t launch_prepare(const ProbDev &P, double *lgy, float *u, float *pt,
+                          hipStream_t stream);
+hipError_t launch_sample(const ProbDev &P, const StepDev &st,
+                         const double *loc, const double *logscale,
+                         const double *eps, uint64_t seed, uint64_t step,
+                         hipStream_t stream);
+hipError_t launch_phi_consts(const ProbDev &P, int S, const double *phi,
+                             float4 *pk, hipStream_t stream);
+hipError_t launch_windows(const ProbDev &P, int S, const double *phi, int *lo,
+                          int *hi, const int *perm, hipStream_t stream);
+hipError_t launch_fused(const ProbDev &P, const StepDev &st, bool grad,
+                        float *f_out, hipStream_t stream);
+hipError_t launch_elbo(const ProbDev &P, const StepDev &st,
+                       const double *logscale, double *elbo_out,
+                       double *loglik_out, hipStream_t stream);
+hipError_t launch_grad(const ProbDev &P, const StepDev &st, double scale,
+                       const double *scale_dev, double *gloc,
+                       double *glogscale, hipStream_t stream);
+
+void set_error(const std::string &msg);
+
+constexpr int kMaxSamples = 1024;
+
+// Bytes of per-step device state for (N, K, T, S), laid out by carve_step.
+size_t step_bytes(int ntiles, int K, int T, int S);
+// Carves StepDev buffers out of `base` (256-byte aligned pieces).
+StepDev carve_step(void *base, int ntiles, int K, int T, int S);
+
+inline int num_tiles(int N) { return (N + kTile - 1) / kTile; }
+
+}  // namespace xrdvi

@@ -165,3 +165,16 @@ def arrival_times(n: int, rate: float, seed: int) -> np.ndarray:
     """Poisson arrival process: cumulative exponential gaps (seconds)."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+def random_phi(K: int, S: int, seed: int, h_max: float = 2.0e4,
+               w_range=(0.03, 0.3)) -> np.ndarray:
+    """Constrained latents [S][4][K] scattered over the prior's range:
+    h ~ U(0, h_max), mu ~ N(0, 0.03), w ~ U(w_range), r ~ U(0, 1)."""
+    rng = np.random.default_rng(seed)
+    phi = np.empty((S, 4, K))
+    phi[:, 0] = rng.uniform(0.0, h_max, (S, K))
+    phi[:, 1] = rng.normal(0.0, 0.03, (S, K))
+    phi[:, 2] = rng.uniform(w_range[0], w_range[1], (S, K))
+    phi[:, 3] = rng.uniform(0.0, 1.0, (S, K))
+    return phi

@@ -1,0 +1,354 @@
+"""Python binding of libxrdvi (ctypes).  Argument marshalling only: every
+step of the computation runs in the library's HIP kernels; PyTorch supplies
+device memory and the current stream.
+
+The functions carry the C names (xrdvi_profile, xrdvi_window_plan,
+xrdvi_elbo_fwd, xrdvi_elbo_bwd, ...).  ``XrdviELBO`` wraps the forward and
+the recomputing adjoint as a ``torch.autograd.Function``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libxrdvi.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "xrdvi.h")
+
+XRDVI_OK, XRDVI_PENDING = 0, 1
+XRDVI_EINVAL, XRDVI_ENOMEM, XRDVI_EDEVICE = -1, -2, -3
+XRDVI_EBUSY, XRDVI_ENOENT, XRDVI_ECANCELED = -4, -5, -6
+
+
+class XrdviError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"xrdvi error {code}: {msg}")
+        self.code = code
+
+
+class Prior(C.Structure):
+    _fields_ = [("lambda_h", C.c_double), ("mu_sd", C.c_double),
+                ("w_shape", C.c_double), ("w_rate", C.c_double)]
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("N", C.c_int32), ("K", C.c_int32),
+                ("x", C.POINTER(C.c_double)), ("y", C.POINTER(C.c_double)),
+                ("bg", C.POINTER(C.c_double)),
+                ("peak_off", C.POINTER(C.c_int32)),
+                ("peak_pos", C.POINTER(C.c_double)),
+                ("peak_int", C.POINTER(C.c_double)),
+                ("cutoff", C.c_double), ("prior", Prior)]
+
+
+_lib = None
+_VP = C.c_void_p
+
+
+def exported_symbols():
+    """Names declared XRDVI_API in include/xrdvi.h."""
+    txt = open(HEADER).read()
+    return re.findall(r"XRDVI_API\s+[\w\s\*]+?\b(xrdvi_\w+)\s*\(", txt)
+
+
+def load():
+    """Loads libxrdvi.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with "
+            "`python -m paper_2501_09308_amd.build` (there is no fallback)")
+    lib = C.CDLL(LIB_PATH)
+    i32, u64, dbl = C.c_int32, C.c_uint64, C.c_double
+    sig = {
+        "xrdvi_last_error": ([], C.c_char_p),
+        "xrdvi_version": ([], C.c_int),
+        "xrdvi_validate": ([C.POINTER(ProblemDesc)], C.c_int),
+        "xrdvi_ctx_create": ([C.c_int, C.POINTER(_VP)], C.c_int),
+        "xrdvi_ctx_destroy": ([_VP], C.c_int),
+        "xrdvi_problem_create": ([_VP, C.POINTER(ProblemDesc), C.POINTER(_VP)], C.c_int),
+        "xrdvi_problem_destroy": ([_VP], C.c_int),
+        "xrdvi_problem_info": ([_VP, C.POINTER(i32), C.POINTER(i32),
+                                C.POINTER(i32), C.POINTER(dbl)], C.c_int),
+        "xrdvi_tape_create": ([_VP, _VP, i32, C.POINTER(_VP)], C.c_int),
+        "xrdvi_tape_destroy": ([_VP], C.c_int),
+        "xrdvi_profile": ([_VP, _VP, i32, _VP, _VP, _VP], C.c_int),
+        "xrdvi_window_plan": ([_VP, _VP, i32, _VP, _VP, _VP, _VP], C.c_int),
+        "xrdvi_elbo_fwd": ([_VP, _VP, i32, _VP, _VP, _VP, u64, u64, i32, _VP,
+                            _VP, _VP, _VP], C.c_int),
+        "xrdvi_elbo_bwd": ([_VP, _VP, dbl, _VP, _VP, _VP, _VP], C.c_int),
+        "xrdvi_tape_samples": ([_VP, _VP, _VP, _VP], C.c_int),
+        "xrdvi_timing_enable": ([_VP, i32], C.c_int),
+        "xrdvi_timing_read": ([_VP, C.POINTER(dbl), C.POINTER(C.c_int64), i32],
+                              C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc < 0:
+        msg = load().xrdvi_last_error().decode(errors="replace")
+        raise XrdviError(rc, msg)
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device=None):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_f64(t, shape, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.contiguous()
+
+
+def make_desc(x, y, bg, peak_off, peak_pos, peak_int, cutoff=0.0,
+              lambda_h=0.0, mu_sd=0.03, w_shape=3.0, w_rate=100.0):
+    """Builds a ProblemDesc over host arrays; returns (desc, keepalive)."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, bg)]
+    off = np.ascontiguousarray(peak_off, dtype=np.int32)
+    pos = np.ascontiguousarray(peak_pos, dtype=np.float64)
+    inten = np.ascontiguousarray(peak_int, dtype=np.float64)
+    if pos.size == 0:
+        pos = np.zeros(1); inten = np.zeros(1)
+    d = ProblemDesc()
+    d.N = len(arrs[0]); d.K = len(off) - 1
+    P = C.POINTER(C.c_double)
+    d.x = arrs[0].ctypes.data_as(P); d.y = arrs[1].ctypes.data_as(P)
+    d.bg = arrs[2].ctypes.data_as(P)
+    d.peak_off = off.ctypes.data_as(C.POINTER(C.c_int32))
+    d.peak_pos = pos.ctypes.data_as(P); d.peak_int = inten.ctypes.data_as(P)
+    d.cutoff = float(cutoff)
+    d.prior = Prior(lambda_h, mu_sd, w_shape, w_rate)
+    return d, (arrs, off, pos, inten)
+
+
+def xrdvi_validate(**kw):
+    d, keep = make_desc(**kw)
+    return _check(load().xrdvi_validate(C.byref(d)))
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        h = _VP()
+        _check(self.lib.xrdvi_ctx_create(int(device), C.byref(h)))
+        self.handle = h
+        self.device = int(device)
+
+    def close(self):
+        if self.handle:
+            self.lib.xrdvi_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def xrdvi_timing_enable(ctx: Context, enable: bool = True):
+    _check(ctx.lib.xrdvi_timing_enable(ctx.handle, 1 if enable else 0))
+
+
+def xrdvi_timing_read(ctx: Context, reset: bool = True):
+    """(total ms, launches) of the fused kernel since the last reset."""
+    ms, n = C.c_double(), C.c_int64()
+    _check(ctx.lib.xrdvi_timing_read(ctx.handle, C.byref(ms), C.byref(n),
+                                     1 if reset else 0))
+    return ms.value, n.value
+
+
+def xrdvi_ctx_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+class Problem:
+    """A prepared problem on the device (xrdvi_problem_create)."""
+
+    def __init__(self, ctx: Context, x, y, bg, peak_off, peak_pos, peak_int,
+                 cutoff=0.0, lambda_h=0.0, mu_sd=0.03, w_shape=3.0,
+                 w_rate=100.0):
+        self.ctx = ctx
+        d, keep = make_desc(x, y, bg, peak_off, peak_pos, peak_int, cutoff,
+                            lambda_h, mu_sd, w_shape, w_rate)
+        h = _VP()
+        _check(ctx.lib.xrdvi_problem_create(ctx.handle, C.byref(d), C.byref(h)))
+        self.handle = h
+        N, K, T, lam = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        _check(ctx.lib.xrdvi_problem_info(h, C.byref(N), C.byref(K), C.byref(T),
+                                          C.byref(lam)))
+        self.N, self.K, self.T, self.lambda_h = N.value, K.value, T.value, lam.value
+        self.cutoff = float(cutoff)
+
+    @classmethod
+    def from_workload(cls, ctx, prob, y, **kw):
+        return cls(ctx, prob.x, y, prob.bg, prob.peak_off, prob.peak_pos,
+                   prob.peak_int, kw.pop("cutoff", prob.cutoff), **kw)
+
+    def close(self):
+        if self.handle:
+            self.ctx.lib.xrdvi_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def xrdvi_problem_create(ctx, *a, **kw) -> Problem:
+    return Problem(ctx, *a, **kw)
+
+
+class Tape:
+    def __init__(self, ctx: Context, prob: Problem, S: int):
+        self.ctx, self.prob, self.S = ctx, prob, int(S)
+        h = _VP()
+        _check(ctx.lib.xrdvi_tape_create(ctx.handle, prob.handle, int(S), C.byref(h)))
+        self.handle = h
+        self.version = 0
+
+    def close(self):
+        if self.handle:
+            self.ctx.lib.xrdvi_tape_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def xrdvi_tape_create(ctx, prob, S) -> Tape:
+    return Tape(ctx, prob, S)
+
+
+def xrdvi_profile(ctx: Context, prob: Problem, phi: torch.Tensor,
+                  out: torch.Tensor | None = None) -> torch.Tensor:
+    """f[S][N] (float32) at constrained phi[S][4][K] (float64, device)."""
+    if phi.dim() == 2:
+        phi = phi.unsqueeze(0)
+    S = phi.shape[0]
+    phi = _dev_f64(phi, (S, 4, prob.K), "phi")
+    if out is None:
+        out = torch.empty((S, prob.N), dtype=torch.float32, device=phi.device)
+    _check(ctx.lib.xrdvi_profile(ctx.handle, prob.handle, S, _ptr(phi), _ptr(out),
+                                 _stream(phi.device)))
+    return out
+
+
+def xrdvi_window_plan(ctx: Context, prob: Problem, phi: torch.Tensor):
+    """(lo, hi) int32 [S][T] in the caller's peak order."""
+    if phi.dim() == 2:
+        phi = phi.unsqueeze(0)
+    S = phi.shape[0]
+    phi = _dev_f64(phi, (S, 4, prob.K), "phi")
+    lo = torch.empty((S, max(prob.T, 1)), dtype=torch.int32, device=phi.device)
+    hi = torch.empty_like(lo)
+    _check(ctx.lib.xrdvi_window_plan(ctx.handle, prob.handle, S, _ptr(phi),
+                                     _ptr(lo), _ptr(hi), _stream(phi.device)))
+    return lo[:, :prob.T], hi[:, :prob.T]
+
+
+def xrdvi_elbo_fwd(ctx: Context, prob: Problem, tape: Tape, loc, logscale,
+                   eps=None, seed=0, step=0, need_grad=True, elbo_out=None,
+                   loglik_out=None):
+    """Returns (elbo [1], loglik [S]) float64 device tensors."""
+    K, S = prob.K, tape.S
+    loc = _dev_f64(loc, (4, K), "loc")
+    logscale = _dev_f64(logscale, (4, K), "logscale")
+    if eps is not None:
+        eps = _dev_f64(eps, (S, 4, K), "eps")
+    dev = loc.device
+    if elbo_out is None:
+        elbo_out = torch.empty(1, dtype=torch.float64, device=dev)
+    if loglik_out is None:
+        loglik_out = torch.empty(S, dtype=torch.float64, device=dev)
+    _check(ctx.lib.xrdvi_elbo_fwd(ctx.handle, prob.handle, S, _ptr(loc),
+                                  _ptr(logscale), _ptr(eps), C.c_uint64(seed),
+                                  C.c_uint64(step), 1 if need_grad else 0,
+                                  _ptr(elbo_out), _ptr(loglik_out), tape.handle,
+                                  _stream(dev)))
+    tape.version += 1
+    return elbo_out, loglik_out
+
+
+def xrdvi_tape_samples(ctx: Context, tape: Tape, out=None):
+    """Constrained samples [S][4][K] of the last forward on `tape`."""
+    if out is None:
+        out = torch.empty((tape.S, 4, tape.prob.K), dtype=torch.float64,
+                          device=torch.device("cuda", ctx.device))
+    _check(ctx.lib.xrdvi_tape_samples(ctx.handle, tape.handle, _ptr(out),
+                                      _stream(out.device)))
+    return out
+
+
+def xrdvi_elbo_bwd(ctx: Context, tape: Tape, grad_scale=1.0,
+                   grad_scale_dev: torch.Tensor | None = None,
+                   grad_loc=None, grad_logscale=None, device=None):
+    K = tape.prob.K
+    dev = device if device is not None else torch.device("cuda", ctx.device)
+    if grad_loc is None:
+        grad_loc = torch.empty((4, K), dtype=torch.float64, device=dev)
+    if grad_logscale is None:
+        grad_logscale = torch.empty((4, K), dtype=torch.float64, device=dev)
+    if grad_scale_dev is not None:
+        grad_scale_dev = grad_scale_dev.to(torch.float64).contiguous()
+    _check(ctx.lib.xrdvi_elbo_bwd(ctx.handle, tape.handle, float(grad_scale),
+                                  _ptr(grad_scale_dev), _ptr(grad_loc),
+                                  _ptr(grad_logscale), _stream(dev)))
+    return grad_loc, grad_logscale
+
+
+class XrdviELBO(torch.autograd.Function):
+    """ELBO estimate as a differentiable function of (loc, logscale).
+
+    Forward runs the fused profile + likelihood + recomputing adjoint; the
+    backward only applies the chain rule to the saved per-tile sums (no
+    S x K x N basis is stored).  One tape holds one pending backward: a
+    second forward on the same tape invalidates the first graph."""
+
+    @staticmethod
+    def forward(fctx, loc, logscale, ctx_, prob, tape, eps, seed, step):
+        need = bool(fctx.needs_input_grad[0] or fctx.needs_input_grad[1])
+        elbo, _ = xrdvi_elbo_fwd(ctx_, prob, tape, loc.detach(),
+                                 logscale.detach(), eps=eps, seed=seed,
+                                 step=step, need_grad=need)
+        fctx.ctx_, fctx.tape = ctx_, tape
+        fctx.version = tape.version
+        return elbo[0]
+
+    @staticmethod
+    def backward(fctx, g):
+        if fctx.tape.version != fctx.version:
+            raise RuntimeError("the tape was reused by a later forward before "
+                               "this backward")
+        gl, gs = xrdvi_elbo_bwd(fctx.ctx_, fctx.tape, 1.0,
+                                grad_scale_dev=g.reshape(1),
+                                device=g.device)
+        return gl, gs, None, None, None, None, None, None
+
+
+def elbo(ctx, prob, tape, loc, logscale, eps=None, seed=0, step=0):
+    return XrdviELBO.apply(loc, logscale, ctx, prob, tape, eps, seed, step)
