@@ -59,12 +59,27 @@ def build(save_temps: str | None = None, verbose: bool = False) -> str:
     return LIB
 
 
+UBENCH_SRC = os.path.join(PKG, "ubench", "ubench.hip")
+UBENCH_LIB = os.path.join(PKG, "ubench", "libxrdvi_ubench.so")
+
+
+def build_ubench(verbose: bool = False) -> str:
+    """Instruction-rate microbenchmarks (a separate library)."""
+    cmd = [HIPCC, *FLAGS, "-shared", UBENCH_SRC, "-o", UBENCH_LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(UBENCH_LIB + ".tmp", UBENCH_LIB)
+    return UBENCH_LIB
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--save-temps", default=None)
     ap.add_argument("-v", "--verbose", action="store_true")
     a = ap.parse_args(argv)
     print(build(a.save_temps, a.verbose))
+    print(build_ubench(a.verbose))
 
 
 if __name__ == "__main__":

@@ -60,6 +60,7 @@ size_t step_bytes(int ntiles, int K, int T, int S) {
     b += align256(sizeof(double) * S * (size_t)ntiles);           // llp
     b += align256(sizeof(float) * 6 * (size_t)ntiles * K * S);    // part
     b += align256(sizeof(double) * D);              // sd
+    b += align256(sizeof(int4) * S * (size_t)ntiles * K);         // rng
     return b;
 }
 
@@ -80,6 +81,7 @@ StepDev carve_step(void *base, int ntiles, int K, int T, int S) {
     st.llp = (double *)take(sizeof(double) * S * (size_t)ntiles);
     st.part = (float *)take(sizeof(float) * 6 * (size_t)ntiles * K * S);
     st.sd = (double *)take(sizeof(double) * D);
+    st.rng = (int4 *)take(sizeof(int4) * S * (size_t)ntiles * K);
     return st;
 }
 
@@ -338,7 +340,9 @@ int xrdvi_problem_create(xrdvi_ctx *ctx, const xrdvi_problem_desc *d,
     P.mu_sd = d->prior.mu_sd;
     P.w_shape = d->prior.w_shape;
     P.w_rate = d->prior.w_rate;
-    P.lgamma_w_shape = std::lgamma(d->prior.w_shape);
+    P.c_h = std::log(lam);
+    P.c_mu = -std::log(d->prior.mu_sd) - 0.5 * std::log(2.0 * M_PI);
+    P.c_w = d->prior.w_shape * std::log(d->prior.w_rate) - std::lgamma(d->prior.w_shape);
     P.x = (const double *)(base + o_x);
     P.y = (const double *)(base + o_y);
     P.bg = (const double *)(base + o_bg);
@@ -431,6 +435,7 @@ int xrdvi_profile(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     HIP_TRY(launch_phi_consts(P, S, phi, st.pk, s), "phi constants");
     if (P.cutoff > 0.0)
         HIP_TRY(launch_windows(P, S, phi, st.lo, st.hi, nullptr, s), "window plan");
+    HIP_TRY(launch_plan(P, st, phi, s), "tile plan");
     HIP_TRY(timed_fused(ctx, P, st, false, f_out, s), "profile");
     return XRDVI_OK;
     API_GUARD_END
@@ -470,6 +475,7 @@ int xrdvi_elbo_fwd(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     HIP_TRY(launch_sample(P, st, loc, logscale, eps, seed, step, s), "sample");
     if (P.cutoff > 0.0)
         HIP_TRY(launch_windows(P, S, st.phi, st.lo, st.hi, nullptr, s), "window plan");
+    HIP_TRY(launch_plan(P, st, st.phi, s), "tile plan");
     HIP_TRY(timed_fused(ctx, P, st, need_grad != 0, nullptr, s),
             "fused profile/adjoint");
     HIP_TRY(launch_elbo(P, st, logscale, elbo_out, loglik_out, s), "elbo");

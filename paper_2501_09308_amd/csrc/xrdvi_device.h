@@ -28,11 +28,11 @@ constexpr int kPPL = 2;                   // 2-theta points per lane
 constexpr int kTile = kWave * kPPL;       // points per tile (one block)
 constexpr int kWaves = 4;                 // waves per block, splitting phases
 constexpr int kBlock = kWave * kWaves;
-constexpr int kChunk = 1024;              // phases per LDS range chunk
-// The Gaussian term is evaluated only while some lane has 1 + q2^2 < this
-// bound; beyond it 2^(-q2^2) < 2^-80 of the peak height, far below the FP32
-// resolution of any profile value f >= B > 0.
-constexpr float kGaussTMax = 81.0f;
+// The Gaussian term of a peak is evaluated for a tile only when the peak
+// lies within kGaussReach FWHM of one of the tile's points: beyond 4.47 w,
+// 2^(-q2^2) < 2^-80 of the peak height, far below the FP32 resolution of
+// any profile value f >= B > 0 (the extra 0.13 w absorbs rounding).
+constexpr double kGaussReach = 4.6;
 
 constexpr double kCG = 0.93943727869965133377;   // 2 sqrt(ln 2 / pi)
 constexpr double kCL = 0.63661977236758134308;   // 2 / pi
@@ -45,7 +45,10 @@ constexpr double kTwoPi = 6.28318530717958647693;
 struct ProbDev {
     int N, K, T, ntiles;
     double cutoff;
-    double lambda, mu_sd, w_shape, w_rate, lgamma_w_shape;
+    double lambda, mu_sd, w_shape, w_rate;
+    // log-density constants: ln lambda, -ln(mu_sd sqrt(2 pi)),
+    // shape ln(rate) - lgamma(shape)
+    double c_h, c_mu, c_w;
     const double *x, *y, *bg, *lgy;   // [N]; lgy = ln y!
     const float *u;                   // [ntiles * kTile] x_i - xref_tile
     const int *off;                   // [K + 1]
@@ -64,6 +67,8 @@ struct StepDev {
     double *lpj;      // [S][K] log prior + log|J|
     double *lpb;      // [S][ceil(K/64)] per-wave sums of lpj
     int *lo, *hi;     // [S][T] window plan (sorted peak order)
+    int4 *rng;        // [S][ntiles][K] peak ranges (ja, ga, gb, jb) of a
+                      // tile: [ja, jb) reach the tile, [ga, gb) need G
     double *llp;      // [S][ntiles] per-tile log-likelihood
     float *part;      // [ntiles][K][S][6] adjoint tile sums
     double *sd;       // [4K] exp(logscale)
@@ -140,15 +145,6 @@ __device__ __forceinline__ float4 phase_consts(double h, double mu, double w,
                        (float)(h * r * kCL * iw), (float)mu);
 }
 
-__device__ __forceinline__ double log_prior_phase(const ProbDev &P, double h,
-                                                  double mu, double w) {
-    const double um = mu / P.mu_sd;
-    return (log(P.lambda) - P.lambda * h)
-         + (-log(P.mu_sd) - 0.5 * kLn2Pi - 0.5 * um * um)
-         + (P.w_shape * log(P.w_rate) - P.lgamma_w_shape
-            + (P.w_shape - 1.0) * log(w) - P.w_rate * w);
-}
-
 // ---- window plan ---------------------------------------------------------
 
 // First i with x[i] >= v.
@@ -186,54 +182,118 @@ __device__ inline int2 window_of(const ProbDev &P, double p, double mu,
     return make_int2(lo, hi);
 }
 
-// Peaks [ja, jb) of phase k whose windows (for sample s) can reach the
-// tile's points [i0, i1): windows are monotone in the sorted peak order.
-__device__ inline int2 tile_peak_range(const int *lo, const int *hi, int a,
-                                       int b, int i0, int i1) {
-    int l = a, r = b;                   // first j with hi[j] > i0
-    while (l < r) {
-        const int mid = (l + r) >> 1;
-        if (hi[mid] > i0) r = mid; else l = mid + 1;
+// ---- per-(sample, tile, phase) peak ranges ---------------------------------
+//
+// Peaks are ordered by position inside each phase, so for a fixed sample
+// the window bounds are monotone in the peak index and both the peaks whose
+// window reaches a tile and the peaks whose Gaussian matters there form
+// contiguous index ranges.
+
+// First j in [a, b) with v[j] > key (v non-decreasing).
+__device__ inline int first_greater(const int *v, int a, int b, int key) {
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (v[mid] > key) b = mid; else a = mid + 1;
     }
-    const int ja = l;
-    r = b;                              // first j with lo[j] >= i1
-    while (l < r) {
-        const int mid = (l + r) >> 1;
-        if (lo[mid] >= i1) r = mid; else l = mid + 1;
+    return a;
+}
+// First j in [a, b) with v[j] >= key.
+__device__ inline int first_not_less(const int *v, int a, int b, int key) {
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (v[mid] >= key) b = mid; else a = mid + 1;
     }
-    return make_int2(ja, l);
+    return a;
+}
+__device__ inline int first_not_less_d(const double *v, int a, int b,
+                                       double key) {
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (v[mid] >= key) b = mid; else a = mid + 1;
+    }
+    return a;
+}
+__device__ inline int first_greater_d(const double *v, int a, int b,
+                                      double key) {
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (v[mid] > key) b = mid; else a = mid + 1;
+    }
+    return a;
+}
+
+// Range entry of (sample s, tile t, phase k); phi: [S][4][K].
+__device__ inline int4 tile_range(const ProbDev &P, const StepDev &st,
+                                  const double *phi, int s, int t, int k) {
+    const int a = P.off[k], b = P.off[k + 1];
+    const int i0 = t * kTile, i1 = min(i0 + kTile, P.N);
+    int ja = a, jb = b;
+    if (P.cutoff > 0.0) {
+        const int *lo = st.lo + (size_t)s * P.T;
+        const int *hi = st.hi + (size_t)s * P.T;
+        ja = first_greater(hi, a, b, i0);
+        jb = first_not_less(lo, ja, b, i1);
+    }
+    const double *ph = phi + (size_t)s * 4 * P.K;
+    const double mu = ph[P.K + k], w = ph[2 * P.K + k];
+    const double reach = kGaussReach * w;
+    // Gaussian relevant: p + mu + reach >= x[i0] and p + mu - reach <= x[i1-1]
+    const int ga = first_not_less_d(P.pos, ja, jb, P.x[i0] - mu - reach);
+    const int gb = first_greater_d(P.pos, ga, jb, P.x[i1 - 1] - mu + reach);
+    return make_int4(ja, ga, gb, jb);
+}
+
+// ---- wave reductions ------------------------------------------------------
+
+template <int CTRL, int ROWS, bool BOUND>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v),
+                                                      CTRL, ROWS, 0xf, BOUND));
+}
+
+// Sum over the 64 lanes with DPP row shifts and row broadcasts (inclusive
+// scan inside each row of 16, then across rows); the total ends in lane 63
+// and is returned as a wave-uniform value.
+__device__ __forceinline__ float wave_total_f32(float v) {
+    v += dpp_f32<0x111, 0xf, true>(v);   // row_shr:1
+    v += dpp_f32<0x112, 0xf, true>(v);   // row_shr:2
+    v += dpp_f32<0x114, 0xf, true>(v);   // row_shr:4
+    v += dpp_f32<0x118, 0xf, true>(v);   // row_shr:8
+    v += dpp_f32<0x142, 0xa, false>(v);  // row_bcast:15
+    v += dpp_f32<0x143, 0xc, false>(v);  // row_bcast:31
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// Keeps a wave-uniform value in a vector register, so that an instruction
+// combining it with a scalar operand needs no extra move.
+__device__ __forceinline__ float in_vgpr(float v) {
+    asm volatile("" : "+v"(v));
+    return v;
 }
 
 struct FusedSmem {
     float sig[kWaves][kTile];
     float rres[kTile];
     double red[kWaves];
-    int2 rng[kChunk];
 };
-
-// Fills smem.rng[0..kn) with the tile's peak range of phases kc..kc+kn-1.
-template <bool WIN>
-__device__ __forceinline__ void load_ranges(const ProbDev &P,
-                                            const StepDev &st, int s, int i0,
-                                            int kc, int kn, FusedSmem &sm) {
-    if (!WIN) return;
-    __syncthreads();
-    const int *lo = st.lo + (size_t)s * P.T;
-    const int *hi = st.hi + (size_t)s * P.T;
-    const int i1 = min(i0 + kTile, P.N);
-    for (int kk = threadIdx.x; kk < kn; kk += kBlock) {
-        const int k = kc + kk;
-        sm.rng[kk] = tile_peak_range(lo, hi, P.off[k], P.off[k + 1], i0, i1);
-    }
-    __syncthreads();
-}
 
 // ---- fused profile + likelihood + adjoint of one (tile, sample) ---------
 //
 // Four waves split the phases (k = wave, wave + 4, ...).  Every wave holds
 // the same kTile points, kPPL per lane (point i0 + p*64 + lane).  Peak data
-// are wave-uniform (scalar loads).  WIN: only peaks whose window reaches
-// the tile are visited and each lane is masked by the exact window.
+// are wave-uniform (scalar loads).  Per phase the peaks run in three
+// segments: [ja, ga) and [gb, jb) need only the Lorentzian, [ga, gb) both
+// components.  WIN: each lane is masked by the peak's exact window.
+template <bool WIN>
+struct PeakMask {
+    int lo, hi;
+    __device__ __forceinline__ float apply(int i, float t) const {
+        if (!WIN) return t;
+        return (unsigned)(i - lo) < (unsigned)(hi - lo) ? t
+                                                        : __builtin_huge_valf();
+    }
+};
+
 template <bool WIN, bool GRAD>
 __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
                            float *f_out, FusedSmem &sm) {
@@ -243,9 +303,10 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int i0 = t * kTile;
     cptr<float> pk = as_const(reinterpret_cast<const float *>(st.pk + (size_t)s * P.K));
+    cptr<int> rg = as_const(reinterpret_cast<const int *>(
+        st.rng + ((size_t)s * P.ntiles + t) * P.K));
     cptr<float> ptt = as_const(P.pt + (size_t)t * P.T);
     cptr<float> inten = as_const(P.inten);
-    cptr<int> off = as_const(P.off);
     cptr<int> wlo = as_const(st.lo + (size_t)s * P.T);
     cptr<int> whi = as_const(st.hi + (size_t)s * P.T);
 
@@ -257,66 +318,54 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
         u[p] = P.u[idx[p]];
     }
 
-    // forward: per-lane partial signal over this wave's phases
+    // ---------------- forward: partial signal over this wave's phases
     float sig[kPPL];
 #pragma unroll
     for (int p = 0; p < kPPL; ++p) sig[p] = 0.f;
 
-    for (int kc = 0; kc < P.K; kc += kChunk) {
-        const int kn = min(kChunk, P.K - kc);
-        load_ranges<WIN>(P, st, s, i0, kc, kn, sm);
-        for (int kk = wv; kk < kn; kk += kWaves) {
-            const int k = kc + kk;
-            int ja, jb;
-            if (WIN) { ja = sm.rng[kk].x; jb = sm.rng[kk].y; }
-            else { ja = off[k]; jb = off[k + 1]; }
-            if (ja >= jb) continue;
-            const float4 c = make_float4(pk[4 * k], pk[4 * k + 1], pk[4 * k + 2],
-                                         pk[4 * k + 3]);
-            float uq[kPPL], accL[kPPL], accG[kPPL];
+    for (int k = wv; k < P.K; k += kWaves) {
+        const int ja = rg[4 * k], ga = rg[4 * k + 1], gb = rg[4 * k + 2],
+                  jb = rg[4 * k + 3];
+        if (ja >= jb) continue;
+        const float iw2 = in_vgpr(pk[4 * k]);
+        const float aG = pk[4 * k + 1], aL = pk[4 * k + 2], mu = pk[4 * k + 3];
+        float uq[kPPL], accL[kPPL], accG[kPPL];
 #pragma unroll
-            for (int p = 0; p < kPPL; ++p) {
-                uq[p] = (u[p] - c.w) * c.x;
-                accL[p] = 0.f;
-                accG[p] = 0.f;
-            }
-            for (int j = ja; j < jb; ++j) {
+        for (int p = 0; p < kPPL; ++p) {
+            uq[p] = (u[p] - mu) * iw2;
+            accL[p] = 0.f;
+            accG[p] = 0.f;
+        }
+        // Lorentzian-only and full segments
+        for (int seg = 0; seg < 3; ++seg) {
+            const int j0 = seg == 0 ? ja : (seg == 1 ? ga : gb);
+            const int j1 = seg == 0 ? ga : (seg == 1 ? gb : jb);
+            const bool gauss = seg == 1;
+#pragma unroll 2
+            for (int j = j0; j < j1; ++j) {
                 const float ptj = ptt[j];
                 const float I = inten[j];
-                float q2[kPPL], tt[kPPL];
-                bool near = false;
+                PeakMask<WIN> mk;
+                if (WIN) { mk.lo = wlo[j]; mk.hi = whi[j]; }
 #pragma unroll
                 for (int p = 0; p < kPPL; ++p) {
-                    q2[p] = fmaf(-ptj, c.x, uq[p]);
-                    tt[p] = fmaf(q2[p], q2[p], 1.0f);
-                    if (WIN) {
-                        const int l0 = wlo[j], l1 = whi[j];
-                        const bool in = (unsigned)(idx[p] - l0) <
-                                        (unsigned)(l1 - l0);
-                        tt[p] = in ? tt[p] : __builtin_huge_valf();
-                    }
-                    near |= tt[p] < kGaussTMax;
-                }
-#pragma unroll
-                for (int p = 0; p < kPPL; ++p)
-                    accL[p] = fmaf(I, rcp_f32(tt[p]), accL[p]);
-                if (__builtin_expect(__any(near), 0)) {
-#pragma unroll
-                    for (int p = 0; p < kPPL; ++p)
-                        accG[p] = fmaf(I, exp2_f32(1.0f - tt[p]), accG[p]);
+                    const float q2 = fmaf(-ptj, iw2, uq[p]);
+                    const float tt = mk.apply(idx[p], fmaf(q2, q2, 1.0f));
+                    accL[p] = fmaf(I, rcp_f32(tt), accL[p]);
+                    if (gauss) accG[p] = fmaf(I, exp2_f32(1.0f - tt), accG[p]);
                 }
             }
-#pragma unroll
-            for (int p = 0; p < kPPL; ++p)
-                sig[p] = fmaf(c.z, accL[p], fmaf(c.y, accG[p], sig[p]));
         }
+#pragma unroll
+        for (int p = 0; p < kPPL; ++p)
+            sig[p] = fmaf(aL, accL[p], fmaf(aG, accG[p], sig[p]));
     }
 
 #pragma unroll
     for (int p = 0; p < kPPL; ++p) sm.sig[wv][p * kWave + lane] = sig[p];
     __syncthreads();
 
-    // point stage: f = B + signal (FP64), log-likelihood, residual
+    // ---------------- point stage: f = B + signal (FP64), likelihood, residual
     double ll = 0.0;
     for (int q = threadIdx.x; q < kTile; q += kBlock) {
         const int i = i0 + q;
@@ -344,75 +393,78 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
     }
     if (!GRAD) return;
 
-    // adjoint: recompute every peak value, six sums per (sample, phase)
+    // ---------------- adjoint: recompute every peak value
+    // per point and phase: yl = sum I l, yl1 = sum I l^2 q2, yl2 = sum I l^2,
+    // ye = sum I e, ye1 = sum I e q2, ye2 = sum I e q2^2; the phase's six
+    // sums are then sum_points (y/f - 1) * (...), reduced over the wave.
     float rres[kPPL];
 #pragma unroll
     for (int p = 0; p < kPPL; ++p) rres[p] = sm.rres[p * kWave + lane];
 
-    for (int kc = 0; kc < P.K; kc += kChunk) {
-        const int kn = min(kChunk, P.K - kc);
-        if (P.K > kChunk) load_ranges<WIN>(P, st, s, i0, kc, kn, sm);
-        for (int kk = wv; kk < kn; kk += kWaves) {
-            const int k = kc + kk;
-            float *dst = st.part + (((size_t)t * P.K + k) * st.S + s) * 6;
-            int ja, jb;
-            if (WIN) { ja = sm.rng[kk].x; jb = sm.rng[kk].y; }
-            else { ja = off[k]; jb = off[k + 1]; }
-            if (ja >= jb) {
-                if (lane < 6) dst[lane] = 0.f;
-                continue;
-            }
-            const float4 c = make_float4(pk[4 * k], pk[4 * k + 1], pk[4 * k + 2],
-                                         pk[4 * k + 3]);
-            float uq[kPPL];
+    for (int k = wv; k < P.K; k += kWaves) {
+        float *dst = st.part + (((size_t)t * P.K + k) * st.S + s) * 6;
+        const int ja = rg[4 * k], ga = rg[4 * k + 1], gb = rg[4 * k + 2],
+                  jb = rg[4 * k + 3];
+        if (ja >= jb) {
+            if (lane < 6) dst[lane] = 0.f;
+            continue;
+        }
+        const float iw2 = in_vgpr(pk[4 * k]);
+        const float mu = pk[4 * k + 3];
+        float uq[kPPL], yl0[kPPL], yl1[kPPL], yl2[kPPL], ye0[kPPL], ye1[kPPL],
+            ye2[kPPL];
 #pragma unroll
-            for (int p = 0; p < kPPL; ++p) uq[p] = (u[p] - c.w) * c.x;
-            float e0 = 0.f, e1 = 0.f, e2 = 0.f, l0s = 0.f, l1s = 0.f, l2s = 0.f;
-            for (int j = ja; j < jb; ++j) {
+        for (int p = 0; p < kPPL; ++p) {
+            uq[p] = (u[p] - mu) * iw2;
+            yl0[p] = yl1[p] = yl2[p] = 0.f;
+            ye0[p] = ye1[p] = ye2[p] = 0.f;
+        }
+        for (int seg = 0; seg < 3; ++seg) {
+            const int j0 = seg == 0 ? ja : (seg == 1 ? ga : gb);
+            const int j1 = seg == 0 ? ga : (seg == 1 ? gb : jb);
+            const bool gauss = seg == 1;
+#pragma unroll 2
+            for (int j = j0; j < j1; ++j) {
                 const float ptj = ptt[j];
                 const float I = inten[j];
-                float q2[kPPL], tt[kPPL];
-                bool near = false;
+                PeakMask<WIN> mk;
+                if (WIN) { mk.lo = wlo[j]; mk.hi = whi[j]; }
 #pragma unroll
                 for (int p = 0; p < kPPL; ++p) {
-                    q2[p] = fmaf(-ptj, c.x, uq[p]);
-                    tt[p] = fmaf(q2[p], q2[p], 1.0f);
-                    if (WIN) {
-                        const int a = wlo[j], b = whi[j];
-                        const bool in = (unsigned)(idx[p] - a) <
-                                        (unsigned)(b - a);
-                        tt[p] = in ? tt[p] : __builtin_huge_valf();
-                    }
-                    near |= tt[p] < kGaussTMax;
-                }
-#pragma unroll
-                for (int p = 0; p < kPPL; ++p) {
-                    const float R = rres[p] * I;
-                    const float l = rcp_f32(tt[p]);
-                    const float Rl = R * l;
-                    const float Rll = Rl * l;
-                    l0s += Rl;
-                    l2s += Rll;
-                    l1s = fmaf(Rll, q2[p], l1s);
-                }
-                if (__builtin_expect(__any(near), 0)) {
-#pragma unroll
-                    for (int p = 0; p < kPPL; ++p) {
-                        const float R = rres[p] * I;
-                        const float Re = R * exp2_f32(1.0f - tt[p]);
-                        const float Req = Re * q2[p];
-                        e0 += Re;
-                        e1 += Req;
-                        e2 = fmaf(Req, q2[p], e2);
+                    const float q2 = fmaf(-ptj, iw2, uq[p]);
+                    const float tt = mk.apply(idx[p], fmaf(q2, q2, 1.0f));
+                    const float l = rcp_f32(tt);
+                    const float Il = I * l;
+                    const float Ill = Il * l;
+                    yl0[p] += Il;
+                    yl2[p] += Ill;
+                    yl1[p] = fmaf(Ill, q2, yl1[p]);
+                    if (gauss) {
+                        const float Ie = I * exp2_f32(1.0f - tt);
+                        const float Ieq = Ie * q2;
+                        ye0[p] += Ie;
+                        ye1[p] += Ieq;
+                        ye2[p] = fmaf(Ieq, q2, ye2[p]);
                     }
                 }
             }
-            e0 = wave_sum(e0); e1 = wave_sum(e1); e2 = wave_sum(e2);
-            l0s = wave_sum(l0s); l1s = wave_sum(l1s); l2s = wave_sum(l2s);
-            if (lane == 0) {
-                dst[0] = e0; dst[1] = e1; dst[2] = e2;
-                dst[3] = l0s; dst[4] = l1s; dst[5] = l2s;
-            }
+        }
+        float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f;
+#pragma unroll
+        for (int p = 0; p < kPPL; ++p) {
+            v0 = fmaf(rres[p], ye0[p], v0);
+            v1 = fmaf(rres[p], ye1[p], v1);
+            v2 = fmaf(rres[p], ye2[p], v2);
+            v3 = fmaf(rres[p], yl0[p], v3);
+            v4 = fmaf(rres[p], yl1[p], v4);
+            v5 = fmaf(rres[p], yl2[p], v5);
+        }
+        v0 = wave_total_f32(v0); v1 = wave_total_f32(v1);
+        v2 = wave_total_f32(v2); v3 = wave_total_f32(v3);
+        v4 = wave_total_f32(v4); v5 = wave_total_f32(v5);
+        if (lane == 0) {
+            dst[0] = v0; dst[1] = v1; dst[2] = v2;
+            dst[3] = v3; dst[4] = v4; dst[5] = v5;
         }
     }
 }

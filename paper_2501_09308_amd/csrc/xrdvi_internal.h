@@ -21,6 +21,8 @@ hipError_t launch_phi_consts(const ProbDev &P, int S, const double *phi,
                              float4 *pk, hipStream_t stream);
 hipError_t launch_windows(const ProbDev &P, int S, const double *phi, int *lo,
                           int *hi, const int *perm, hipStream_t stream);
+hipError_t launch_plan(const ProbDev &P, const StepDev &st, const double *phi,
+                       hipStream_t stream);
 hipError_t launch_fused(const ProbDev &P, const StepDev &st, bool grad,
                         float *f_out, hipStream_t stream);
 hipError_t launch_elbo(const ProbDev &P, const StepDev &st,

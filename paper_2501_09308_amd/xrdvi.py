@@ -16,7 +16,9 @@ import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libxrdvi.so")
+# XRDVI_LIB selects another build of the same library (e.g. to compare
+# kernel variants); the default is the in-tree build.
+LIB_PATH = os.environ.get("XRDVI_LIB", os.path.join(_PKG, "libxrdvi.so"))
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "xrdvi.h")
 
 XRDVI_OK, XRDVI_PENDING = 0, 1
