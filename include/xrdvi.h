@@ -52,7 +52,8 @@ enum {
     XRDVI_EDEVICE = -3,    /* a HIP runtime call failed                     */
     XRDVI_EBUSY = -4,      /* serving queue full                            */
     XRDVI_ENOENT = -5,     /* unknown ticket                                */
-    XRDVI_ECANCELED = -6   /* request cancelled                             */
+    XRDVI_ECANCELED = -6,  /* request cancelled                             */
+    XRDVI_ENONFINITE = -7  /* an analysis produced a non-finite ELBO        */
 };
 
 typedef struct xrdvi_ctx xrdvi_ctx;
@@ -190,6 +191,98 @@ XRDVI_API int xrdvi_elbo_bwd(xrdvi_ctx *ctx, const xrdvi_tape *tape,
                              double grad_scale, const double *grad_scale_dev,
                              double *grad_loc, double *grad_logscale,
                              void *stream);
+
+/*
+ * Adam ascent step (Kingma & Ba 2015) on n coordinates, the optimiser of
+ * the stochastic VI loop (the paper runs 1000 optimisation steps, Sec. 4):
+ *   m1 = b1 m1 + (1-b1) g,  m2 = b2 m2 + (1-b2) g^2,
+ *   theta += lr (m1 / (1 - b1^t)) / (sqrt(m2 / (1 - b2^t)) + eps)
+ * theta, m1, m2 (updated in place), grad: device double [n]; t >= 1.
+ */
+XRDVI_API int xrdvi_adam_step(xrdvi_ctx *ctx, int32_t n, double *theta,
+                              double *m1, double *m2, const double *grad,
+                              int32_t t, double lr, double beta1, double beta2,
+                              double eps, void *stream);
+
+/* ---- serving: continuous batching of whole analyses ------------------------
+ *
+ * An analysis is `steps` stochastic-VI optimisation steps (ELBO forward,
+ * adjoint gradient, Adam with beta = (0.9, 0.999), eps = 1e-8) of one
+ * problem with S samples per step; the noise of step n is Philox4x32-10
+ * keyed by (seed, n) as in xrdvi_elbo_fwd, so the result depends only on
+ * the request.  The server keeps each admitted analysis's problem and
+ * variational state resident in a device arena, admits queued requests in
+ * arrival order as soon as a slot and arena memory are free, and advances
+ * all resident analyses together with batched kernels (optionally replayed
+ * from one captured hipGraph).
+ */
+typedef struct {
+    xrdvi_problem_desc problem;     /* host pointers, copied at submit       */
+    int32_t S;                      /* samples per step, 1..1024             */
+    int32_t steps;                  /* optimisation steps, >= 1              */
+    uint64_t seed;                  /* noise key                             */
+    double lr;                      /* Adam step size; 0 selects 1e-2        */
+    const double *init_loc;         /* host [4][K] or NULL: m_h = ln(0.01 /
+                                       lambda), m_mu = 0, m_w = ln 0.1,
+                                       m_r = 0                               */
+    const double *init_logscale;    /* host [4][K] or NULL: ln 0.1           */
+    double *out_loc;                /* host [4][K] or NULL; written before
+                                       poll reports completion              */
+    double *out_logscale;           /* host [4][K] or NULL                   */
+    double *out_elbo_trace;         /* host [steps] or NULL: ELBO per step   */
+} xrdvi_request;
+
+typedef struct {
+    int32_t state;        /* XRDVI_PENDING, XRDVI_OK or a negative error     */
+    int32_t steps_done;
+    double t_arrive;      /* seconds on the server clock: submit, ...        */
+    double t_admit;       /* ... admission (-1 before), ...                  */
+    double t_done;        /* ... completion (-1 before)                      */
+    double final_elbo;    /* ELBO estimate of the last step                  */
+} xrdvi_status;
+
+typedef struct {
+    int32_t device;
+    int32_t max_slots;         /* analyses resident at once, 1..512          */
+    int32_t max_queue;         /* queued requests before XRDVI_EBUSY         */
+    int32_t steps_per_launch;  /* optimisation steps per batched launch      */
+    int32_t use_graph;         /* non-zero: replay the steps from a hipGraph */
+    void *arena;               /* device memory for resident analyses, or
+                                  NULL to let the server allocate it         */
+    size_t arena_bytes;
+} xrdvi_server_config;
+
+/* Creates a server with its own stream (default priority) and scheduler
+ * thread.  A caller-supplied arena must stay valid until destroy. */
+XRDVI_API int xrdvi_server_create(const xrdvi_server_config *cfg,
+                                  xrdvi_server **out);
+/* Cancels everything not finished, joins the scheduler, frees resources. */
+XRDVI_API int xrdvi_server_destroy(xrdvi_server *srv);
+/* Queues a request (host inputs copied; the caller may free them on
+ * return).  XRDVI_EINVAL for an invalid problem or parameters,
+ * XRDVI_ENOMEM if it can never fit the arena, XRDVI_EBUSY if the queue is
+ * full.  Thread-safe. */
+XRDVI_API int xrdvi_submit(xrdvi_server *srv, const xrdvi_request *req,
+                           uint64_t *ticket);
+/* XRDVI_PENDING while queued or running; XRDVI_OK once the outputs have
+ * been written (reported once: the ticket is then forgotten and later
+ * polls return XRDVI_ENOENT); XRDVI_ECANCELED, XRDVI_ENONFINITE or
+ * XRDVI_EDEVICE when it failed.  `st` (may be NULL) receives the state and
+ * the time stamps.  Thread-safe. */
+XRDVI_API int xrdvi_poll(xrdvi_server *srv, uint64_t ticket,
+                         xrdvi_status *st);
+/* Cancels a queued or running request (its outputs are not written).
+ * Thread-safe. */
+XRDVI_API int xrdvi_cancel(xrdvi_server *srv, uint64_t ticket);
+/* Current time (seconds) on the clock of the status time stamps. */
+XRDVI_API double xrdvi_server_clock(xrdvi_server *srv);
+
+/* One analysis at a time on `stream`, with the per-step launches of
+ * xrdvi_elbo_fwd / xrdvi_elbo_bwd / xrdvi_adam_step: the sequential
+ * reference of the serving loop (same kernels and noise keys).
+ * Synchronous; fills the request's outputs and *st. */
+XRDVI_API int xrdvi_plain_run(xrdvi_ctx *ctx, const xrdvi_request *req,
+                              xrdvi_status *st, void *stream);
 
 /*
  * Copies the constrained samples phi_s = T(z_s) drawn by the last

@@ -30,7 +30,8 @@ FLAGS = [
 
 
 def sources():
-    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip"))
+                  + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
 def build(save_temps: str | None = None, verbose: bool = False) -> str:

@@ -1,0 +1,188 @@
+// Batched optimisation step over every resident analysis of the server.
+//
+// Persistent kernels with fixed grids: each reads the slot table and the
+// per-kernel work prefix from device memory, so one captured graph serves
+// any membership.  Unit u of a kernel belongs to resident slot i when
+// pre[i] <= u < pre[i + 1]; units of analyses that have run all their steps
+// do nothing.  The per-unit work is the same device code as the
+// single-analysis kernels, and the noise of step n of an analysis is keyed
+// by (its seed, n), so an analysis computes the same result alone or in
+// any mix.
+#include "batch.h"
+#include "xrdvi_steps.h"
+
+namespace xrdvi {
+
+namespace {
+
+// Stages the prefix of kernel `kind` and the slot ids in LDS.
+struct PrefixSmem {
+    int pre[kMaxSlots + 1];
+    int slot[kMaxSlots];
+    int n;
+};
+
+__device__ void load_prefix(const SchedDev *sch, int kind, PrefixSmem &ps) {
+    const int n = sch->n;
+    for (int i = threadIdx.x; i <= n; i += blockDim.x) ps.pre[i] = sch->pre[kind][i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) ps.slot[i] = sch->slot[i];
+    if (threadIdx.x == 0) ps.n = n;
+    __syncthreads();
+}
+
+// Resident index i with pre[i] <= u < pre[i + 1].
+__device__ int find_slot(const PrefixSmem &ps, int u) {
+    int lo = 0, hi = ps.n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (ps.pre[mid] <= u) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline bool running(const SlotDev &d) { return *d.step < d.steps; }
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void kb_sample(const SlotDev *tab,
+                                                 const SchedDev *sch) {
+    __shared__ PrefixSmem ps;
+    __shared__ SampleSmem sm;
+    load_prefix(sch, kSample, ps);
+    const int total = ps.pre[ps.n];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int i = find_slot(ps, u);
+        const SlotDev &d = tab[ps.slot[i]];
+        if (!running(d)) continue;
+        const int local = u - ps.pre[i];
+        const int nkb = (d.P.K + kWave - 1) / kWave;
+        sample_block(d.P, d.st, d.loc, d.logscale, nullptr, d.seed,
+                     (uint64_t)*d.step, local / nkb, local % nkb, nkb, sm);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void kb_windows(const SlotDev *tab,
+                                                  const SchedDev *sch) {
+    __shared__ PrefixSmem ps;
+    load_prefix(sch, kWindows, ps);
+    const int total = ps.pre[ps.n];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int i = find_slot(ps, u);
+        const SlotDev &d = tab[ps.slot[i]];
+        if (!running(d)) continue;
+        const size_t g = (size_t)(u - ps.pre[i]) * 256 + threadIdx.x;
+        if (g < (size_t)d.st.S * d.P.T)
+            windows_elem(d.P, d.st.phi, d.st.lo, d.st.hi, nullptr, g);
+    }
+}
+
+__global__ __launch_bounds__(256) void kb_plan(const SlotDev *tab,
+                                               const SchedDev *sch) {
+    __shared__ PrefixSmem ps;
+    load_prefix(sch, kPlan, ps);
+    const int total = ps.pre[ps.n];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int i = find_slot(ps, u);
+        const SlotDev &d = tab[ps.slot[i]];
+        if (!running(d)) continue;
+        const size_t g = (size_t)(u - ps.pre[i]) * 256 + threadIdx.x;
+        if (g < (size_t)d.st.S * d.P.ntiles * d.P.K) plan_elem(d.P, d.st, d.st.phi, g);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void kb_fused(const SlotDev *tab,
+                                                   const SchedDev *sch) {
+    __shared__ PrefixSmem ps;
+    __shared__ FusedSmem sm;
+    load_prefix(sch, kFused, ps);
+    const int total = ps.pre[ps.n];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int i = find_slot(ps, u);
+        const SlotDev &d = tab[ps.slot[i]];
+        if (!running(d)) continue;
+        const int local = u - ps.pre[i];
+        const int t = local % d.P.ntiles, s = local / d.P.ntiles;
+        if (d.P.cutoff > 0.0) fused_tile<true, false>(d.P, d.st, t, s, nullptr, sm);
+        else fused_tile<false, true>(d.P, d.st, t, s, nullptr, sm);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void kb_adjoint(const SlotDev *tab,
+                                                     const SchedDev *sch) {
+    __shared__ PrefixSmem ps;
+    __shared__ double red[kWaves][6];
+    load_prefix(sch, kAdjoint, ps);
+    const int total = ps.pre[ps.n];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int i = find_slot(ps, u);
+        const SlotDev &d = tab[ps.slot[i]];
+        if (!running(d)) continue;
+        const int local = u - ps.pre[i];
+        adjoint_phase(d.P, d.st, local / d.P.K, local % d.P.K, red);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(1024) void kb_elbo(const SlotDev *tab,
+                                                const SchedDev *sch) {
+    __shared__ PrefixSmem ps;
+    __shared__ ElboSmem sm;
+    load_prefix(sch, kElbo, ps);
+    const int total = ps.pre[ps.n];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int i = find_slot(ps, u);
+        const SlotDev &d = tab[ps.slot[i]];
+        if (!running(d)) continue;
+        const double e = elbo_block(d.P, d.st, d.logscale, nullptr, sm);
+        if (threadIdx.x == 0) d.trace[*d.step] = e;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void kb_grad_adam(const SlotDev *tab,
+                                                    const SchedDev *sch) {
+    __shared__ PrefixSmem ps;
+    __shared__ GradSmem sm;
+    load_prefix(sch, kGrad, ps);
+    const int total = ps.pre[ps.n];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int i = find_slot(ps, u);
+        const SlotDev &d = tab[ps.slot[i]];
+        if (!running(d)) continue;
+        AdamArgs a;
+        a.m1_loc = d.m1_loc; a.m2_loc = d.m2_loc;
+        a.m1_ls = d.m1_ls; a.m2_ls = d.m2_ls;
+        a.t = *d.step + 1;
+        a.lr = d.lr; a.b1 = 0.9; a.b2 = 0.999; a.eps = 1e-8;
+        grad_block(d.P, d.st, u - ps.pre[i], 1.0, nullptr, nullptr, nullptr,
+                   d.loc, d.logscale, &a, sm);
+        __syncthreads();
+    }
+}
+
+// Last kernel of a step: every running analysis moves to its next step.
+__global__ void kb_advance(const SlotDev *tab, const SchedDev *sch) {
+    const int n = sch->n;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += gridDim.x * blockDim.x) {
+        const SlotDev &d = tab[sch->slot[i]];
+        if (*d.step < d.steps) *d.step += 1;
+    }
+}
+
+hipError_t launch_batch_step(const SlotDev *tab, const SchedDev *sch,
+                             hipStream_t s) {
+    kb_sample<<<kGridSmall, 256, 0, s>>>(tab, sch);
+    kb_windows<<<kGridLarge, 256, 0, s>>>(tab, sch);
+    kb_plan<<<kGridLarge, 256, 0, s>>>(tab, sch);
+    kb_fused<<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    kb_adjoint<<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    kb_elbo<<<kGridElbo, 1024, 0, s>>>(tab, sch);
+    kb_grad_adam<<<kGridLarge, 256, 0, s>>>(tab, sch);
+    kb_advance<<<1, 1024, 0, s>>>(tab, sch);
+    return hipGetLastError();
+}
+
+}  // namespace xrdvi

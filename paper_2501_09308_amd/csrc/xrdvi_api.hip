@@ -47,7 +47,7 @@ void set_error(const std::string &msg) { g_err = msg; }
 
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-size_t step_bytes(int ntiles, int K, int T, int S) {
+size_t step_bytes(int ntiles, int K, int T, int S, int N) {
     const size_t D = 4 * (size_t)K;
     const size_t kb = (K + kWave - 1) / kWave;
     size_t b = 0;
@@ -61,10 +61,12 @@ size_t step_bytes(int ntiles, int K, int T, int S) {
     b += align256(sizeof(float) * 6 * (size_t)ntiles * K * S);    // part
     b += align256(sizeof(double) * D);              // sd
     b += align256(sizeof(int4) * S * (size_t)ntiles * K);         // rng
+    b += align256(sizeof(float) * S * (size_t)N);                 // rres
+    b += align256(sizeof(double) * 6 * (size_t)K * S);            // pw
     return b;
 }
 
-StepDev carve_step(void *base, int ntiles, int K, int T, int S) {
+StepDev carve_step(void *base, int ntiles, int K, int T, int S, int N) {
     char *p = static_cast<char *>(base);
     const size_t D = 4 * (size_t)K;
     const size_t kb = (K + kWave - 1) / kWave;
@@ -82,7 +84,92 @@ StepDev carve_step(void *base, int ntiles, int K, int T, int S) {
     st.part = (float *)take(sizeof(float) * 6 * (size_t)ntiles * K * S);
     st.sd = (double *)take(sizeof(double) * D);
     st.rng = (int4 *)take(sizeof(int4) * S * (size_t)ntiles * K);
+    st.rres = (float *)take(sizeof(float) * S * (size_t)N);
+    st.pw = (double *)take(sizeof(double) * 6 * (size_t)K * S);
     return st;
+}
+
+// Device layout of a prepared problem, in 256-byte aligned pieces.
+struct ProblemLayout {
+    size_t x, y, bg, lgy, u, off, ph, pos, inten, pt, perm, total;
+};
+
+static ProblemLayout problem_layout(int N, int K, int T) {
+    const int nt = num_tiles(N);
+    const size_t T1 = (size_t)std::max(T, 1);
+    ProblemLayout L{};
+    size_t o = 0;
+    auto slot = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
+    L.x = slot(8 * (size_t)N); L.y = slot(8 * (size_t)N);
+    L.bg = slot(8 * (size_t)N); L.lgy = slot(8 * (size_t)N);
+    L.u = slot(4 * (size_t)nt * kTile); L.off = slot(4 * (size_t)(K + 1));
+    L.ph = slot(4 * T1); L.pos = slot(8 * T1); L.inten = slot(4 * T1);
+    L.pt = slot(4 * (size_t)nt * T1); L.perm = slot(4 * T1);
+    L.total = o;
+    return L;
+}
+
+size_t problem_bytes(int N, int K, int T) { return problem_layout(N, K, T).total; }
+
+hipError_t upload_problem(const xrdvi_problem_desc &d, double lambda,
+                          char *base, ProbDev &P, int **perm_out,
+                          hipStream_t stream) {
+    const int N = d.N, K = d.K, T = d.peak_off[K];
+    const int T1 = std::max(T, 1);
+    const ProblemLayout L = problem_layout(N, K, T);
+    // peaks ordered by position within each phase (stable)
+    std::vector<int> perm(T1, 0), phase(T1, 0);
+    std::vector<double> pos(T1, 0.0);
+    std::vector<float> inten(T1, 0.f);
+    for (int k = 0; k < K; ++k) {
+        const int a = d.peak_off[k], b = d.peak_off[k + 1];
+        std::iota(perm.begin() + a, perm.begin() + b, a);
+        std::stable_sort(perm.begin() + a, perm.begin() + b, [&](int i, int j) {
+            return d.peak_pos[i] < d.peak_pos[j];
+        });
+        for (int j = a; j < b; ++j) {
+            phase[j] = k;
+            pos[j] = d.peak_pos[perm[j]];
+            inten[j] = (float)d.peak_int[perm[j]];
+        }
+    }
+    auto up = [&](size_t o, const void *src, size_t bytes) {
+        return hipMemcpyAsync(base + o, src, bytes, hipMemcpyHostToDevice, stream);
+    };
+    hipError_t e = up(L.x, d.x, 8 * (size_t)N);
+    if (e == hipSuccess) e = up(L.y, d.y, 8 * (size_t)N);
+    if (e == hipSuccess) e = up(L.bg, d.bg, 8 * (size_t)N);
+    if (e == hipSuccess) e = up(L.off, d.peak_off, 4 * (size_t)(K + 1));
+    if (e == hipSuccess) e = up(L.ph, phase.data(), 4 * (size_t)T1);
+    if (e == hipSuccess) e = up(L.pos, pos.data(), 8 * (size_t)T1);
+    if (e == hipSuccess) e = up(L.inten, inten.data(), 4 * (size_t)T1);
+    if (e == hipSuccess) e = up(L.perm, perm.data(), 4 * (size_t)T1);
+    // pageable sources: complete the copies before the vectors go away
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return e;
+    P = ProbDev{};
+    P.N = N; P.K = K; P.T = T; P.ntiles = num_tiles(N);
+    P.cutoff = d.cutoff;
+    P.lambda = lambda;
+    P.mu_sd = d.prior.mu_sd;
+    P.w_shape = d.prior.w_shape;
+    P.w_rate = d.prior.w_rate;
+    P.c_h = std::log(lambda);
+    P.c_mu = -std::log(d.prior.mu_sd) - 0.5 * std::log(2.0 * M_PI);
+    P.c_w = d.prior.w_shape * std::log(d.prior.w_rate) - std::lgamma(d.prior.w_shape);
+    P.x = (const double *)(base + L.x);
+    P.y = (const double *)(base + L.y);
+    P.bg = (const double *)(base + L.bg);
+    P.lgy = (const double *)(base + L.lgy);
+    P.u = (const float *)(base + L.u);
+    P.off = (const int *)(base + L.off);
+    P.phase = (const int *)(base + L.ph);
+    P.pos = (const double *)(base + L.pos);
+    P.inten = (const float *)(base + L.inten);
+    P.pt = (const float *)(base + L.pt);
+    if (perm_out) *perm_out = (int *)(base + L.perm);
+    return launch_prepare(P, (double *)(base + L.lgy), (float *)(base + L.u),
+                          (float *)(base + L.pt), stream);
 }
 
 }  // namespace xrdvi
@@ -118,7 +205,8 @@ int hip_fail(hipError_t e, const char *what) {
     } while (0)
 
 // Host validation of a problem description; resolves lambda_h.
-int validate_desc(const xrdvi_problem_desc *d, double *lambda_out) {
+int validate_desc(const xrdvi_problem_desc *d, double *lambda_out,
+                  double *ymax_out = nullptr) {
     if (!d) return fail(XRDVI_EINVAL, "problem description is NULL");
     if (d->N < 1) return fail(XRDVI_EINVAL, "N must be >= 1");
     if (d->K < 1) return fail(XRDVI_EINVAL, "K must be >= 1");
@@ -160,15 +248,16 @@ int validate_desc(const xrdvi_problem_desc *d, double *lambda_out) {
         || !std::isfinite(pr.w_rate))
         return fail(XRDVI_EINVAL, "prior.w_shape and prior.w_rate must be > 0");
     double lam = pr.lambda_h;
+    double m = -INFINITY;
+    for (int i = 0; i < d->N; ++i) m = std::max(m, d->y[i] - d->bg[i]);
     if (lam == 0.0) {
-        double m = -INFINITY;
-        for (int i = 0; i < d->N; ++i) m = std::max(m, d->y[i] - d->bg[i]);
         if (!(m > 0.0))
             return fail(XRDVI_EINVAL,
                         "max(y - bg) must be > 0 when prior.lambda_h = 0");
         lam = 1.0 / m;
     }
     if (lambda_out) *lambda_out = lam;
+    if (ymax_out) *ymax_out = m;
     return XRDVI_OK;
 }
 
@@ -218,6 +307,11 @@ bool ensure_ws(xrdvi_ctx *ctx, size_t bytes, int *rc) {
 }
 
 }  // namespace
+
+int xrdvi::validate_problem(const xrdvi_problem_desc *d, double *lambda_out,
+                            double *ymax) {
+    return validate_desc(d, lambda_out, ymax);
+}
 
 #define API_GUARD_BEGIN try {
 #define API_GUARD_END                                                  \
@@ -279,87 +373,21 @@ int xrdvi_problem_create(xrdvi_ctx *ctx, const xrdvi_problem_desc *d,
     int rc = validate_desc(d, &lam);
     if (rc != XRDVI_OK) return rc;
     DeviceGuard g(ctx->device);
-    const int N = d->N, K = d->K, T = d->peak_off[K];
-    const int nt = num_tiles(N);
-    const int T1 = std::max(T, 1);
-
-    // peaks ordered by position within each phase (stable)
-    std::vector<int> perm(T1, 0), phase(T1, 0);
-    std::vector<double> pos(T1, 0.0);
-    std::vector<float> inten(T1, 0.f);
-    for (int k = 0; k < K; ++k) {
-        const int a = d->peak_off[k], b = d->peak_off[k + 1];
-        std::iota(perm.begin() + a, perm.begin() + b, a);
-        std::stable_sort(perm.begin() + a, perm.begin() + b, [&](int i, int j) {
-            return d->peak_pos[i] < d->peak_pos[j];
-        });
-        for (int j = a; j < b; ++j) {
-            phase[j] = k;
-            pos[j] = d->peak_pos[perm[j]];
-            inten[j] = (float)d->peak_int[perm[j]];
-        }
-    }
-
-    size_t off = 0;
-    auto slot = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
-    const size_t o_x = slot(8 * (size_t)N), o_y = slot(8 * (size_t)N),
-                 o_bg = slot(8 * (size_t)N), o_lgy = slot(8 * (size_t)N),
-                 o_u = slot(4 * (size_t)nt * kTile), o_off = slot(4 * (size_t)(K + 1)),
-                 o_ph = slot(4 * (size_t)T1), o_pos = slot(8 * (size_t)T1),
-                 o_int = slot(4 * (size_t)T1), o_pt = slot(4 * (size_t)nt * T1),
-                 o_perm = slot(4 * (size_t)T1);
+    const size_t bytes = problem_bytes(d->N, d->K, d->peak_off[d->K]);
     void *mem = nullptr;
-    hipError_t e = hipMalloc(&mem, off);
+    hipError_t e = hipMalloc(&mem, bytes);
     if (e != hipSuccess)
         return fail(XRDVI_ENOMEM, std::string("problem allocation: ") + hipGetErrorString(e));
-    char *base = static_cast<char *>(mem);
-    auto up = [&](size_t o, const void *src, size_t bytes) {
-        return hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice);
-    };
-    e = up(o_x, d->x, 8 * (size_t)N);
-    if (e == hipSuccess) e = up(o_y, d->y, 8 * (size_t)N);
-    if (e == hipSuccess) e = up(o_bg, d->bg, 8 * (size_t)N);
-    if (e == hipSuccess) e = up(o_off, d->peak_off, 4 * (size_t)(K + 1));
-    if (e == hipSuccess) e = up(o_ph, phase.data(), 4 * (size_t)T1);
-    if (e == hipSuccess) e = up(o_pos, pos.data(), 8 * (size_t)T1);
-    if (e == hipSuccess) e = up(o_int, inten.data(), 4 * (size_t)T1);
-    if (e == hipSuccess) e = up(o_perm, perm.data(), 4 * (size_t)T1);
-    if (e != hipSuccess) {
-        (void)hipFree(mem);
-        return hip_fail(e, "problem upload");
-    }
     auto *pb = new xrdvi_problem();
     pb->ctx = ctx;
     pb->device = ctx->device;
     pb->mem = mem;
-    pb->perm = (int *)(base + o_perm);
-    ProbDev &P = pb->P;
-    P.N = N; P.K = K; P.T = T; P.ntiles = nt;
-    P.cutoff = d->cutoff;
-    P.lambda = lam;
-    P.mu_sd = d->prior.mu_sd;
-    P.w_shape = d->prior.w_shape;
-    P.w_rate = d->prior.w_rate;
-    P.c_h = std::log(lam);
-    P.c_mu = -std::log(d->prior.mu_sd) - 0.5 * std::log(2.0 * M_PI);
-    P.c_w = d->prior.w_shape * std::log(d->prior.w_rate) - std::lgamma(d->prior.w_shape);
-    P.x = (const double *)(base + o_x);
-    P.y = (const double *)(base + o_y);
-    P.bg = (const double *)(base + o_bg);
-    P.lgy = (const double *)(base + o_lgy);
-    P.u = (const float *)(base + o_u);
-    P.off = (const int *)(base + o_off);
-    P.phase = (const int *)(base + o_ph);
-    P.pos = (const double *)(base + o_pos);
-    P.inten = (const float *)(base + o_int);
-    P.pt = (const float *)(base + o_pt);
-    e = launch_prepare(P, (double *)(base + o_lgy), (float *)(base + o_u),
-                       (float *)(base + o_pt), nullptr);
+    e = upload_problem(*d, lam, static_cast<char *>(mem), pb->P, &pb->perm, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
         (void)hipFree(mem);
         delete pb;
-        return hip_fail(e, "problem preparation");
+        return hip_fail(e, "problem upload");
     }
     *out = pb;
     return XRDVI_OK;
@@ -394,7 +422,7 @@ int xrdvi_tape_create(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     if (S < 1 || S > kMaxSamples) return fail(XRDVI_EINVAL, "S must be in [1, 1024]");
     DeviceGuard g(ctx->device);
     const ProbDev &P = prob->P;
-    const size_t bytes = step_bytes(P.ntiles, P.K, P.T, S);
+    const size_t bytes = step_bytes(P.ntiles, P.K, P.T, S, P.N);
     void *mem = nullptr;
     hipError_t e = hipMalloc(&mem, bytes);
     if (e != hipSuccess)
@@ -403,7 +431,7 @@ int xrdvi_tape_create(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     t->prob = prob;
     t->device = ctx->device;
     t->mem = mem;
-    t->st = carve_step(mem, P.ntiles, P.K, P.T, S);
+    t->st = carve_step(mem, P.ntiles, P.K, P.T, S, P.N);
     *out = t;
     return XRDVI_OK;
     API_GUARD_END
@@ -429,8 +457,8 @@ int xrdvi_profile(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     DeviceGuard g(ctx->device);
     const ProbDev &P = prob->P;
     int rc = XRDVI_OK;
-    if (!ensure_ws(ctx, step_bytes(P.ntiles, P.K, P.T, S), &rc)) return rc;
-    StepDev st = carve_step(ctx->ws, P.ntiles, P.K, P.T, S);
+    if (!ensure_ws(ctx, step_bytes(P.ntiles, P.K, P.T, S, P.N), &rc)) return rc;
+    StepDev st = carve_step(ctx->ws, P.ntiles, P.K, P.T, S, P.N);
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(launch_phi_consts(P, S, phi, st.pk, s), "phi constants");
     if (P.cutoff > 0.0)

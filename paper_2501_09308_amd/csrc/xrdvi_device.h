@@ -69,6 +69,9 @@ struct StepDev {
     int *lo, *hi;     // [S][T] window plan (sorted peak order)
     int4 *rng;        // [S][ntiles][K] peak ranges (ja, ga, gb, jb) of a
                       // tile: [ja, jb) reach the tile, [ga, gb) need G
+    float *rres;      // [S][N] residual y/f - 1 (windowed mode)
+    double *pw;       // [K][S][6] adjoint sums per (phase, sample)
+                      // (windowed mode)
     double *llp;      // [S][ntiles] per-tile log-likelihood
     float *part;      // [ntiles][K][S][6] adjoint tile sums
     double *sd;       // [4K] exp(logscale)
@@ -379,6 +382,7 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
             const double y = P.y[i];
             ll += (y != 0.0 ? y * log(f) : 0.0) - f - P.lgy[i];
             rr = (float)(y / f - 1.0);
+            if (st.rres) st.rres[(size_t)s * P.N + i] = rr;
         }
         sm.rres[q] = rr;
     }
@@ -466,6 +470,68 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
             dst[0] = v0; dst[1] = v1; dst[2] = v2;
             dst[3] = v3; dst[4] = v4; dst[5] = v5;
         }
+    }
+}
+
+// ---- peak-major adjoint (windowed mode) -----------------------------------
+//
+// One block of kWaves waves per (sample s, phase k); wave w takes peaks
+// a + w, a + w + kWaves, ...  For every peak the lanes cover consecutive
+// points of its window (64 at a time); x - rho is formed in FP64 and
+// rounded to FP32.  Six sums accumulate per lane over the wave's peaks, are
+// reduced over the wave, then over the waves in fixed order.
+__device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
+                                     int s, int k, double (*red)[6]) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int K = P.K;
+    const double *ph = st.phi + (size_t)s * 4 * K;
+    const double mu = ph[K + k];
+    const float iw2 = (float)(2.0 / ph[2 * K + k]);
+    const float *__restrict__ rres = st.rres + (size_t)s * P.N;
+    cptr<int> wlo = as_const(st.lo + (size_t)s * P.T);
+    cptr<int> whi = as_const(st.hi + (size_t)s * P.T);
+    cptr<double> pos = as_const(P.pos);
+    cptr<float> inten = as_const(P.inten);
+    const int a = P.off[k], b = P.off[k + 1];
+    float e0 = 0.f, e1 = 0.f, e2 = 0.f, l0 = 0.f, l1 = 0.f, l2 = 0.f;
+    for (int j = a + wv; j < b; j += kWaves) {
+        const int lo = wlo[j], hi = whi[j];
+        const float I = inten[j];
+        const double rho = pos[j] + mu;
+        for (int c = lo; c < hi; c += kWave) {
+            const int i = c + lane;
+            const bool valid = i < hi;
+            const int ii = valid ? i : lo;
+            const float R = valid ? rres[ii] * I : 0.f;
+            const float q2 = (float)(P.x[ii] - rho) * iw2;
+            const float tt = fmaf(q2, q2, 1.0f);
+            const float l = rcp_f32(tt);
+            const float Rl = R * l;
+            const float Rll = Rl * l;
+            l0 += Rl;
+            l2 += Rll;
+            l1 = fmaf(Rll, q2, l1);
+            if (__builtin_expect(__any(valid && tt < 81.0f), 0)) {
+                const float Re = R * exp2_f32(1.0f - tt);
+                const float Req = Re * q2;
+                e0 += Re;
+                e1 += Req;
+                e2 = fmaf(Req, q2, e2);
+            }
+        }
+    }
+    e0 = wave_total_f32(e0); e1 = wave_total_f32(e1); e2 = wave_total_f32(e2);
+    l0 = wave_total_f32(l0); l1 = wave_total_f32(l1); l2 = wave_total_f32(l2);
+    if (lane == 0) {
+        red[wv][0] = e0; red[wv][1] = e1; red[wv][2] = e2;
+        red[wv][3] = l0; red[wv][4] = l1; red[wv][5] = l2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double v = 0.0;
+        for (int w = 0; w < kWaves; ++w) v += red[w][threadIdx.x];
+        st.pw[((size_t)k * st.S + s) * 6 + threadIdx.x] = v;
     }
 }
 

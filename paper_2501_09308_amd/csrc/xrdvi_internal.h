@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "xrdvi.h"
 #include "xrdvi_device.h"
 
 namespace xrdvi {
@@ -32,15 +33,31 @@ hipError_t launch_grad(const ProbDev &P, const StepDev &st, double scale,
                        const double *scale_dev, double *gloc,
                        double *glogscale, hipStream_t stream);
 
+hipError_t launch_adam(int n, double *theta, double *m1, double *m2,
+                       const double *g, int t, double lr, double b1, double b2,
+                       double eps, hipStream_t stream);
+
 void set_error(const std::string &msg);
 
 constexpr int kMaxSamples = 1024;
 
 // Bytes of per-step device state for (N, K, T, S), laid out by carve_step.
-size_t step_bytes(int ntiles, int K, int T, int S);
+size_t step_bytes(int ntiles, int K, int T, int S, int N);
 // Carves StepDev buffers out of `base` (256-byte aligned pieces).
-StepDev carve_step(void *base, int ntiles, int K, int T, int S);
+StepDev carve_step(void *base, int ntiles, int K, int T, int S, int N);
 
 inline int num_tiles(int N) { return (N + kTile - 1) / kTile; }
+
+// Device bytes of a prepared problem and its upload (validated desc,
+// resolved lambda) into `base`; fills P and the sorted-to-caller peak
+// permutation.  Synchronises `stream` before returning (pageable sources).
+size_t problem_bytes(int N, int K, int T);
+hipError_t upload_problem(const xrdvi_problem_desc &d, double lambda,
+                          char *base, ProbDev &P, int **perm_out,
+                          hipStream_t stream);
+// Host validation of a problem description; resolves lambda_h (0 -> 1 /
+// max(y - bg)) and returns max(y - bg) in *ymax when non-NULL.
+int validate_problem(const xrdvi_problem_desc *d, double *lambda_out,
+                     double *ymax);
 
 }  // namespace xrdvi

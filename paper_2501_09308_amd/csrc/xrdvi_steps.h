@@ -1,0 +1,266 @@
+// Per-step work units shared by the single-analysis kernels and the
+// batched serving kernels (each unit is what one block or one thread does).
+#pragma once
+
+#include "xrdvi_device.h"
+
+namespace xrdvi {
+
+// ---- a1: sample and transform ---------------------------------------------
+//
+// Block of 256 threads = 64 phases x 4 latent types of sample s, phases
+// kb*64 .. kb*64+63.  Each thread draws one coordinate
+// z = loc + exp(logscale) eps, maps it to its constrained value and adds
+// its log prior + log|dphi/dz| term; the first wave then writes the FP32
+// kernel constants and the block's sum of those terms.
+struct SampleSmem {
+    double val[4][kWave];
+    double lpt[4][kWave];
+};
+
+__device__ inline void sample_block(const ProbDev &P, const StepDev &st,
+                                    const double *__restrict__ loc,
+                                    const double *__restrict__ logscale,
+                                    const double *__restrict__ eps_in,
+                                    uint64_t seed, uint64_t step, int s, int kb,
+                                    int nkb, SampleSmem &sm) {
+#pragma clang fp contract(off)
+    const int t = threadIdx.x / kWave, kk = threadIdx.x % kWave;
+    const int k = kb * kWave + kk;
+    const int K = P.K, D = 4 * K;
+    double v = 0.0, lp = 0.0;
+    if (k < K) {
+        const int j = t * K + k;
+        const double e = eps_in ? eps_in[(size_t)s * D + j]
+                                : philox_normal(seed, step, s, j);
+        const double sd = exp(logscale[j]);
+        const double dz = sd * e;
+        const double z = loc[j] + dz;
+        st.eps[(size_t)s * D + j] = e;
+        if (s == 0) st.sd[j] = sd;
+        if (t == 0) {            // h = e^z, h ~ Exp(lambda); |dh/dz| = h
+            v = exp(z);
+            lp = P.c_h - P.lambda * v + z;
+        } else if (t == 1) {     // mu = z, mu ~ N(0, mu_sd)
+            const double um = z / P.mu_sd;
+            v = z;
+            lp = P.c_mu - 0.5 * um * um;
+        } else if (t == 2) {     // w = e^z, w ~ Gamma(shape, rate); |dw/dz| = w
+            v = exp(z);
+            lp = P.c_w + (P.w_shape - 1.0) * z - P.w_rate * v + z;
+        } else {                 // r = logistic(z), r ~ U(0,1); |dr/dz| = r(1-r)
+            v = 1.0 / (1.0 + exp(-z));
+            lp = -softplus(-z) - softplus(z);
+        }
+        st.phi[(size_t)s * D + j] = v;
+    }
+    sm.val[t][kk] = v;
+    sm.lpt[t][kk] = lp;
+    __syncthreads();
+    if (t == 0) {
+        double lpk = 0.0;
+        if (k < K) {
+            st.pk[(size_t)s * K + k] = phase_consts(sm.val[0][kk], sm.val[1][kk],
+                                                    sm.val[2][kk], sm.val[3][kk]);
+            lpk = sm.lpt[0][kk] + sm.lpt[1][kk] + sm.lpt[2][kk] + sm.lpt[3][kk];
+            st.lpj[(size_t)s * K + k] = lpk;
+        }
+        lpk = wave_sum(lpk);
+        if (kk == 0) st.lpb[(size_t)s * nkb + kb] = lpk;
+    }
+}
+
+// ---- a2: window plan element g = s * T + j ---------------------------------
+__device__ inline void windows_elem(const ProbDev &P, const double *phi,
+                                    int *lo, int *hi, const int *perm,
+                                    size_t g) {
+    const int s = (int)(g / P.T), j = (int)(g % P.T);
+    const int k = P.phase[j];
+    const double *ph = phi + (size_t)s * 4 * P.K;
+    const int2 wnd = window_of(P, P.pos[j], ph[P.K + k], ph[2 * P.K + k]);
+    const size_t o = (size_t)s * P.T + (perm ? perm[j] : j);
+    lo[o] = wnd.x;
+    hi[o] = wnd.y;
+}
+
+// ---- a2 (cont.): range element g = (s * ntiles + t) * K + k ---------------
+__device__ inline void plan_elem(const ProbDev &P, const StepDev &st,
+                                 const double *phi, size_t g) {
+    const int k = (int)(g % P.K);
+    const size_t st_idx = g / P.K;
+    const int t = (int)(st_idx % P.ntiles), s = (int)(st_idx / P.ntiles);
+    st.rng[g] = tile_range(P, st, phi, s, t, k);
+}
+
+// ---- a5: ELBO assembly, block of 1024 threads --------------------------------
+//
+// Each sample is summed by a group of G consecutive lanes (G a power of
+// two, G * S <= 1024) and the groups combine with a butterfly; totals over
+// samples use a fixed tree.
+struct ElboSmem {
+    double tot[1024];
+    double red[1024 / kWave];
+};
+
+__device__ inline double elbo_block(const ProbDev &P, const StepDev &st,
+                                    const double *__restrict__ logscale,
+                                    double *loglik_out, ElboSmem &sm) {
+#pragma clang fp contract(off)
+    const int S = st.S;
+    int G = 1;
+    while (G < kWave && 2 * G * S <= 1024) G *= 2;
+    const int tid = threadIdx.x, s = tid / G, g = tid % G;
+    const int kb = (P.K + kWave - 1) / kWave;
+    double l = 0.0, p = 0.0;
+    if (s < S) {
+        for (int t = g; t < P.ntiles; t += G) l += st.llp[(size_t)s * P.ntiles + t];
+        for (int b = g; b < kb; b += G) p += st.lpb[(size_t)s * kb + b];
+    }
+    for (int o = G / 2; o >= 1; o >>= 1) {
+        l += __shfl_xor(l, o, kWave);
+        p += __shfl_xor(p, o, kWave);
+    }
+    sm.tot[tid] = 0.0;
+    __syncthreads();
+    if (g == 0 && s < S) {
+        if (loglik_out) loglik_out[s] = l;
+        sm.tot[s] = l + p;
+    }
+    double ent = 0.0;
+    for (int j = tid; j < 4 * P.K; j += 1024) ent += logscale[j];
+    ent = wave_sum(ent);
+    if ((tid & (kWave - 1)) == 0) sm.red[tid / kWave] = ent;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if (tid < w) sm.tot[tid] += sm.tot[tid + w];
+        __syncthreads();
+    }
+    double e = 0.0;
+    for (int w = 0; w < 1024 / kWave; ++w) e += sm.red[w];
+    const double D = 4.0 * P.K;
+    return sm.tot[0] / S + e + 0.5 * D * (1.0 + kLn2Pi);   // valid in all threads
+}
+
+// ---- a8: Adam (Kingma & Ba) ascent step on one coordinate --------------------
+struct AdamArgs {
+    double *m1_loc, *m2_loc, *m1_ls, *m2_ls;   // [4K] moment estimates
+    int t;                                      // 1-based step
+    double lr, b1, b2, eps;
+};
+
+__device__ inline void adam_update(double &theta, double &m1, double &m2,
+                                   double g, int t, double lr, double b1,
+                                   double b2, double eps) {
+#pragma clang fp contract(off)
+    m1 = b1 * m1 + (1.0 - b1) * g;
+    m2 = b2 * m2 + (1.0 - b2) * g * g;
+    const double mh = m1 / (1.0 - pow(b1, (double)t));
+    const double vh = m2 / (1.0 - pow(b2, (double)t));
+    theta += lr * mh / (sqrt(vh) + eps);
+}
+
+// ---- a7: gradient of phase k, block of 256 threads ----------------------------
+//
+// SG = min(S, 64) samples per pass, 256 / SG threads per sample each summing
+// a stripe of tiles (dense) or reading the phase's sums (windowed); stripes,
+// samples and tiles are combined in FP64 in fixed order, then the chain
+// rule runs through the prior, Jacobian and reparameterisation.  With
+// `adam`, the gradient of the phase's 8 parameters updates loc/logscale
+// in place instead of being stored.
+struct GradSmem {
+    double red[256][6];
+};
+
+__device__ inline void grad_block(const ProbDev &P, const StepDev &st, int k,
+                                  double scale, const double *scale_dev,
+                                  double *gloc, double *glogscale,
+                                  double *loc, double *logscale,
+                                  const AdamArgs *adam, GradSmem &sm) {
+#pragma clang fp contract(off)
+    const int K = P.K, D = 4 * K, S = st.S;
+    const int SG = S < kWave ? S : kWave;
+    const int G = 256 / SG;
+    const int tid = threadIdx.x, sl = tid % SG, g = tid / SG;
+    double am[4] = {0, 0, 0, 0}, as[4] = {0, 0, 0, 0};
+    for (int s0 = 0; s0 < S; s0 += SG) {
+        const int s = s0 + sl;
+        double E[6] = {0, 0, 0, 0, 0, 0};
+        if (g < G && s < S) {
+            if (P.cutoff > 0.0) {
+                if (g == 0) {
+                    const double *src = st.pw + ((size_t)k * S + s) * 6;
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) E[c] = src[c];
+                }
+            } else {
+                for (int t = g; t < P.ntiles; t += G) {
+                    const float *src = st.part + (((size_t)t * K + k) * S + s) * 6;
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) E[c] += (double)src[c];
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sm.red[tid][c] = E[c];
+        __syncthreads();
+        if (g == 0 && s < S) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) E[c] = 0.0;
+            for (int gg = 0; gg < G; ++gg)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) E[c] += sm.red[gg * SG + sl][c];
+            const double *ph = st.phi + (size_t)s * D;
+            const double h = ph[k], mu = ph[K + k], w = ph[2 * K + k],
+                         r = ph[3 * K + k];
+            const double iw = 1.0 / w, iw2 = iw * iw;
+            // d lnL / d(h, mu, w, r) from the six sums
+            // E0 = sum R e, E1 = sum R e q2, E2 = sum R e q2^2,
+            // L0 = sum R l, L1 = sum R l^2 q2, L2 = sum R l^2, R = (y/f - 1) I
+            const double gh = (1.0 - r) * kCG * iw * E[0] + r * kCL * iw * E[3];
+            const double gmu = h * iw2 * ((1.0 - r) * kCG * 4.0 * kLn2 * E[1]
+                                          + r * kCL * 4.0 * E[4]);
+            const double gw = h * iw2 * ((1.0 - r) * kCG * (2.0 * kLn2 * E[2] - E[0])
+                                         + r * kCL * (E[3] - 2.0 * E[5]));
+            const double gr = h * iw * (kCL * E[3] - kCG * E[0]);
+            double gz[4];
+            gz[0] = h * gh - P.lambda * h + 1.0;
+            gz[1] = gmu - mu / (P.mu_sd * P.mu_sd);
+            gz[2] = w * gw + (P.w_shape - 1.0) - P.w_rate * w + 1.0;
+            gz[3] = r * (1.0 - r) * gr + 1.0 - 2.0 * r;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int j = t * K + k;
+                am[t] += gz[t];
+                as[t] += gz[t] * st.eps[(size_t)s * D + j] * st.sd[j];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid < kWave) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            am[t] = wave_sum(am[t]);
+            as[t] = wave_sum(as[t]);
+        }
+        if (tid == 0) {
+            if (scale_dev) scale *= *scale_dev;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int j = t * K + k;
+                const double gl = scale * (am[t] / S);
+                const double gs = scale * (as[t] / S + 1.0);
+                if (adam) {
+                    adam_update(loc[j], adam->m1_loc[j], adam->m2_loc[j], gl,
+                                adam->t, adam->lr, adam->b1, adam->b2, adam->eps);
+                    adam_update(logscale[j], adam->m1_ls[j], adam->m2_ls[j], gs,
+                                adam->t, adam->lr, adam->b1, adam->b2, adam->eps);
+                } else {
+                    gloc[j] = gl;
+                    glogscale[j] = gs;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace xrdvi

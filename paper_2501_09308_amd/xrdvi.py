@@ -47,6 +47,29 @@ class ProblemDesc(C.Structure):
                 ("cutoff", C.c_double), ("prior", Prior)]
 
 
+_DP = C.POINTER(C.c_double)
+
+
+class Request(C.Structure):
+    _fields_ = [("problem", ProblemDesc), ("S", C.c_int32),
+                ("steps", C.c_int32), ("seed", C.c_uint64), ("lr", C.c_double),
+                ("init_loc", _DP), ("init_logscale", _DP), ("out_loc", _DP),
+                ("out_logscale", _DP), ("out_elbo_trace", _DP)]
+
+
+class Status(C.Structure):
+    _fields_ = [("state", C.c_int32), ("steps_done", C.c_int32),
+                ("t_arrive", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double), ("final_elbo", C.c_double)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("device", C.c_int32), ("max_slots", C.c_int32),
+                ("max_queue", C.c_int32), ("steps_per_launch", C.c_int32),
+                ("use_graph", C.c_int32), ("arena", C.c_void_p),
+                ("arena_bytes", C.c_size_t)]
+
+
 _lib = None
 _VP = C.c_void_p
 
@@ -86,6 +109,16 @@ def load():
                             _VP, _VP, _VP], C.c_int),
         "xrdvi_elbo_bwd": ([_VP, _VP, dbl, _VP, _VP, _VP, _VP], C.c_int),
         "xrdvi_tape_samples": ([_VP, _VP, _VP, _VP], C.c_int),
+        "xrdvi_adam_step": ([_VP, i32, _VP, _VP, _VP, _VP, i32, dbl, dbl, dbl,
+                             dbl, _VP], C.c_int),
+        "xrdvi_server_create": ([C.POINTER(ServerConfig), C.POINTER(_VP)], C.c_int),
+        "xrdvi_server_destroy": ([_VP], C.c_int),
+        "xrdvi_submit": ([_VP, C.POINTER(Request), C.POINTER(C.c_uint64)], C.c_int),
+        "xrdvi_poll": ([_VP, C.c_uint64, C.POINTER(Status)], C.c_int),
+        "xrdvi_cancel": ([_VP, C.c_uint64], C.c_int),
+        "xrdvi_server_clock": ([_VP], C.c_double),
+        "xrdvi_plain_run": ([_VP, C.POINTER(Request), C.POINTER(Status), _VP],
+                            C.c_int),
         "xrdvi_timing_enable": ([_VP, i32], C.c_int),
         "xrdvi_timing_read": ([_VP, C.POINTER(dbl), C.POINTER(C.c_int64), i32],
                               C.c_int),
@@ -354,3 +387,123 @@ class XrdviELBO(torch.autograd.Function):
 
 def elbo(ctx, prob, tape, loc, logscale, eps=None, seed=0, step=0):
     return XrdviELBO.apply(loc, logscale, ctx, prob, tape, eps, seed, step)
+
+
+def xrdvi_adam_step(ctx: Context, theta, m1, m2, grad, t, lr=1e-2, beta1=0.9,
+                    beta2=0.999, eps=1e-8):
+    """In-place Adam ascent step on float64 CUDA tensors."""
+    for name, a in (("theta", theta), ("m1", m1), ("m2", m2), ("grad", grad)):
+        if not (a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    _check(ctx.lib.xrdvi_adam_step(ctx.handle, theta.numel(), _ptr(theta),
+                                   _ptr(m1), _ptr(m2), _ptr(grad), int(t),
+                                   float(lr), float(beta1), float(beta2),
+                                   float(eps), _stream(theta.device)))
+
+
+class _Submission:
+    """Host buffers of one request, kept alive until it completes."""
+
+    def __init__(self, x, y, bg, peak_off, peak_pos, peak_int, cutoff, S,
+                 steps, seed, lr, init, prior):
+        self.desc, self.keep = make_desc(x, y, bg, peak_off, peak_pos,
+                                         peak_int, cutoff, **prior)
+        K = len(peak_off) - 1
+        self.loc = np.zeros((4, K))
+        self.logscale = np.zeros((4, K))
+        self.trace = np.zeros(int(steps))
+        self.init = None
+        if init is not None:
+            self.init = [np.ascontiguousarray(a, dtype=np.float64) for a in init]
+        r = Request()
+        r.problem = self.desc
+        r.S, r.steps, r.seed, r.lr = int(S), int(steps), int(seed), float(lr)
+        if self.init is not None:
+            r.init_loc = self.init[0].ctypes.data_as(_DP)
+            r.init_logscale = self.init[1].ctypes.data_as(_DP)
+        r.out_loc = self.loc.ctypes.data_as(_DP)
+        r.out_logscale = self.logscale.ctypes.data_as(_DP)
+        r.out_elbo_trace = self.trace.ctypes.data_as(_DP)
+        self.req = r
+
+
+def _request_args(prob, y, S, steps, seed, lr=0.0, init=None, cutoff=None,
+                  **prior):
+    return (prob.x, y, prob.bg, prob.peak_off, prob.peak_pos, prob.peak_int,
+            prob.cutoff if cutoff is None else cutoff, S, steps, seed, lr,
+            init, prior)
+
+
+class Server:
+    """xrdvi_server: continuous batching of whole analyses (see xrdvi.h)."""
+
+    def __init__(self, device=0, max_slots=64, max_queue=1 << 16,
+                 steps_per_launch=10, use_graph=True, arena=None,
+                 arena_bytes=None):
+        self.lib = load()
+        cfg = ServerConfig()
+        cfg.device, cfg.max_slots, cfg.max_queue = device, max_slots, max_queue
+        cfg.steps_per_launch, cfg.use_graph = steps_per_launch, 1 if use_graph else 0
+        if arena is not None:
+            cfg.arena = C.c_void_p(arena.data_ptr())
+            cfg.arena_bytes = arena.numel() * arena.element_size()
+        else:
+            cfg.arena = None
+            cfg.arena_bytes = int(arena_bytes or (8 << 30))
+        self._arena = arena
+        h = _VP()
+        _check(self.lib.xrdvi_server_create(C.byref(cfg), C.byref(h)))
+        self.handle = h
+        self._subs = {}
+
+    def submit(self, prob, y, S, steps, seed, lr=0.0, init=None, **kw):
+        sub = _Submission(*_request_args(prob, y, S, steps, seed, lr, init, **kw))
+        t = C.c_uint64()
+        _check(self.lib.xrdvi_submit(self.handle, C.byref(sub.req), C.byref(t)))
+        self._subs[t.value] = sub
+        return t.value
+
+    def poll(self, ticket):
+        """(state, status dict, outputs or None).  Outputs are returned once
+        the request is done: dict(loc, logscale, trace)."""
+        st = Status()
+        rc = self.lib.xrdvi_poll(self.handle, C.c_uint64(ticket), C.byref(st))
+        if rc == XRDVI_ENOENT:
+            raise XrdviError(rc, "unknown ticket")
+        info = dict(state=st.state, steps_done=st.steps_done,
+                    t_arrive=st.t_arrive, t_admit=st.t_admit, t_done=st.t_done,
+                    final_elbo=st.final_elbo)
+        out = None
+        if rc != XRDVI_PENDING:
+            sub = self._subs.pop(ticket)
+            if rc == XRDVI_OK:
+                out = dict(loc=sub.loc, logscale=sub.logscale, trace=sub.trace)
+        return rc, info, out
+
+    def cancel(self, ticket):
+        _check(self.lib.xrdvi_cancel(self.handle, C.c_uint64(ticket)))
+
+    def clock(self):
+        return self.lib.xrdvi_server_clock(self.handle)
+
+    def close(self):
+        if self.handle:
+            self.lib.xrdvi_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def xrdvi_plain_run(ctx: Context, prob, y, S, steps, seed, lr=0.0, init=None,
+                    **kw):
+    """One analysis with per-step launches (the sequential reference)."""
+    sub = _Submission(*_request_args(prob, y, S, steps, seed, lr, init, **kw))
+    st = Status()
+    _check(ctx.lib.xrdvi_plain_run(ctx.handle, C.byref(sub.req), C.byref(st),
+                                   _stream()))
+    return dict(loc=sub.loc, logscale=sub.logscale, trace=sub.trace,
+                final_elbo=st.final_elbo)
