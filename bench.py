@@ -125,6 +125,89 @@ def run_cpu(W, prob, y, S_total, target_s=15.0):
                         f"({pts:.3g} peak-points, {dt:.1f} s)"))
 
 
+def serving_requests(X, W, ctx, n, seed):
+    """The serving mix: n requests (N, step, K, peaks per phase drawn per
+    request, windows at 8 FWHM) with counts drawn around the HIP profile
+    of each request's generating phases."""
+    reqs = []
+    for i in range(n):
+        prob = W.make_serving_problem(seed + i)
+        P0 = X.Problem(ctx, prob.x, np.ones(prob.N), prob.bg, prob.peak_off,
+                       prob.peak_pos, prob.peak_int, 0.0, lambda_h=1.0)
+        import torch
+        phi = torch.as_tensor(prob.phi_true[None], device="cuda")
+        fstar = X.xrdvi_profile(ctx, P0, phi)[0].double().cpu().numpy()
+        P0.close()
+        reqs.append((prob, W.poisson_counts(fstar, seed + 7919 * (i + 1))))
+    return reqs
+
+
+def pct(v, q):
+    return float(np.percentile(np.asarray(v), q))
+
+
+def run_serving(X, W, ctx, n, rate, steps, S, seed, max_slots, per_launch):
+    """Continuous batching vs one analysis at a time on the same arrival
+    trace; returns both summaries."""
+    reqs = serving_requests(X, W, ctx, n, seed)
+    arrivals = W.arrival_times(n, rate, seed)
+    # ---- served
+    srv = X.Server(max_slots=max_slots, steps_per_launch=per_launch,
+                   use_graph=True, arena_bytes=24 << 30)
+    tickets, results = [], {}
+    t0 = time.perf_counter()
+    nxt = 0
+    while len(results) < n:
+        now = time.perf_counter() - t0
+        while nxt < n and arrivals[nxt] <= now:
+            p, y = reqs[nxt]
+            tickets.append(srv.submit(p, y, S, steps, seed + nxt))
+            nxt += 1
+        for t in tickets:
+            if t in results:
+                continue
+            rc, info, out = srv.poll(t)
+            if rc != X.XRDVI_PENDING:
+                if rc != X.XRDVI_OK:
+                    raise RuntimeError(f"serving request failed: {rc}")
+                results[t] = (info, out)
+        time.sleep(0.0005)
+    srv.close()
+    infos = [results[t][0] for t in tickets]
+    ttr = [i["t_done"] - i["t_arrive"] for i in infos]
+    span = max(i["t_done"] for i in infos) - min(i["t_arrive"] for i in infos)
+    served = dict(analyses_per_s=n / span, p50_s=pct(ttr, 50), p99_s=pct(ttr, 99),
+                  makespan_s=span, max_slots=max_slots,
+                  steps_per_graph_replay=per_launch)
+    log(f"[bench] served: {served}")
+    # ---- plain: one at a time, per-step launches, same kernels and noise keys
+    done, ttr_p = [], []
+    t0 = time.perf_counter()
+    first = None
+    for i, (p, y) in enumerate(reqs):
+        while time.perf_counter() - t0 < arrivals[i]:
+            time.sleep(0.0002)
+        out = X.xrdvi_plain_run(ctx, p, y, S, steps, seed + i)
+        t = time.perf_counter() - t0
+        ttr_p.append(t - arrivals[i])
+        done.append(t)
+        if first is None:
+            first = out
+        if (i + 1) % 64 == 0:
+            log(f"[bench] plain: {i + 1}/{n} done at {t:.1f} s")
+    span_p = done[-1] - arrivals[0]
+    plain = dict(analyses_per_s=n / span_p, p50_s=pct(ttr_p, 50),
+                 p99_s=pct(ttr_p, 99), makespan_s=span_p)
+    log(f"[bench] plain: {plain}")
+    same = float(np.max(np.abs(results[tickets[0]][1]["loc"] - first["loc"])))
+    return dict(workload=(f"serving mix: {n} analyses, Poisson arrivals at "
+                          f"{rate:g}/s, N in [2000,12000], K in [20,300], "
+                          f"20-80 peaks/phase, S={S}, c=8, {steps} steps each"),
+                served=served, plain=plain,
+                speedup_analyses_per_s=served["analyses_per_s"] / plain["analyses_per_s"],
+                max_abs_diff_first_result_vs_plain=same)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +215,12 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle baseline")
+    ap.add_argument("--serving", type=int, default=512,
+                    help="analyses in the serving comparison (0 = skip)")
+    ap.add_argument("--serving-steps", type=int, default=300)
+    ap.add_argument("--serving-rate", type=float, default=40.0)
+    ap.add_argument("--max-slots", type=int, default=128)
+    ap.add_argument("--steps-per-launch", type=int, default=10)
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print("bench.py measures one GPU only: the path runs on a single "
@@ -203,6 +292,11 @@ def main(argv=None):
         },
         "context_1000_steps_s": ms_step,   # 1000 steps x ms/step / 1000
     }
+    if a.serving > 0:
+        log(f"[bench] serving: {a.serving} analyses")
+        out["serving"] = run_serving(X, W, ctx, a.serving, a.serving_rate,
+                                     a.serving_steps, 32, 4000, a.max_slots,
+                                     a.steps_per_launch)
     if rank == 0 and not a.no_cpu:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = run_cpu(W, prob, dense["y"], S)

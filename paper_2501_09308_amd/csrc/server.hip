@@ -53,7 +53,7 @@ SlotLayout slot_layout(const Job &j) {
     const int T = j.off[j.K];
     L.prob = 0;
     L.step = a256(problem_bytes(j.N, j.K, T));
-    L.state = L.step + a256(step_bytes(num_tiles(j.N), j.K, T, j.S, j.N));
+    L.state = L.step + a256(step_bytes(num_tiles(j.N), j.K, T, j.S, j.N, j.cutoff == 0.0));
     L.trace = L.state + a256(sizeof(double) * 6 * 4 * (size_t)j.K);
     L.total = L.trace + a256(sizeof(double) * (size_t)j.steps);
     return L;
@@ -102,7 +102,8 @@ class GpuExecutor : public Executor {
         hipError_t e = upload_problem(desc, j.lambda_h, base + L.prob, d.P, nullptr,
                                       stream_);
         if (e != hipSuccess) return dev_fail(e, "upload");
-        d.st = carve_step(base + L.step, d.P.ntiles, j.K, d.P.T, j.S, j.N);
+        d.st = carve_step(base + L.step, d.P.ntiles, j.K, d.P.T, j.S, j.N,
+                          j.cutoff == 0.0);
         if (d.P.cutoff == 0.0) d.st.rres = nullptr;   // dense: no residual array
         const size_t D = 4 * (size_t)j.K;
         double *state = (double *)(base + L.state);

@@ -47,7 +47,7 @@ void set_error(const std::string &msg) { g_err = msg; }
 
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-size_t step_bytes(int ntiles, int K, int T, int S, int N) {
+size_t step_bytes(int ntiles, int K, int T, int S, int N, bool dense) {
     const size_t D = 4 * (size_t)K;
     const size_t kb = (K + kWave - 1) / kWave;
     size_t b = 0;
@@ -58,7 +58,7 @@ size_t step_bytes(int ntiles, int K, int T, int S, int N) {
     b += align256(sizeof(double) * S * kb);         // lpb
     b += 2 * align256(sizeof(int) * S * (size_t)std::max(T, 1));  // lo, hi
     b += align256(sizeof(double) * S * (size_t)ntiles);           // llp
-    b += align256(sizeof(float) * 6 * (size_t)ntiles * K * S);    // part
+    b += align256(dense ? sizeof(float) * 6 * (size_t)ntiles * K * S : 4);  // part
     b += align256(sizeof(double) * D);              // sd
     b += align256(sizeof(int4) * S * (size_t)ntiles * K);         // rng
     b += align256(sizeof(float) * S * (size_t)N);                 // rres
@@ -66,7 +66,8 @@ size_t step_bytes(int ntiles, int K, int T, int S, int N) {
     return b;
 }
 
-StepDev carve_step(void *base, int ntiles, int K, int T, int S, int N) {
+StepDev carve_step(void *base, int ntiles, int K, int T, int S, int N,
+                   bool dense) {
     char *p = static_cast<char *>(base);
     const size_t D = 4 * (size_t)K;
     const size_t kb = (K + kWave - 1) / kWave;
@@ -81,7 +82,7 @@ StepDev carve_step(void *base, int ntiles, int K, int T, int S, int N) {
     st.lo = (int *)take(sizeof(int) * S * (size_t)std::max(T, 1));
     st.hi = (int *)take(sizeof(int) * S * (size_t)std::max(T, 1));
     st.llp = (double *)take(sizeof(double) * S * (size_t)ntiles);
-    st.part = (float *)take(sizeof(float) * 6 * (size_t)ntiles * K * S);
+    st.part = (float *)take(dense ? sizeof(float) * 6 * (size_t)ntiles * K * S : 4);
     st.sd = (double *)take(sizeof(double) * D);
     st.rng = (int4 *)take(sizeof(int4) * S * (size_t)ntiles * K);
     st.rres = (float *)take(sizeof(float) * S * (size_t)N);
@@ -422,7 +423,7 @@ int xrdvi_tape_create(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     if (S < 1 || S > kMaxSamples) return fail(XRDVI_EINVAL, "S must be in [1, 1024]");
     DeviceGuard g(ctx->device);
     const ProbDev &P = prob->P;
-    const size_t bytes = step_bytes(P.ntiles, P.K, P.T, S, P.N);
+    const size_t bytes = step_bytes(P.ntiles, P.K, P.T, S, P.N, P.cutoff == 0.0);
     void *mem = nullptr;
     hipError_t e = hipMalloc(&mem, bytes);
     if (e != hipSuccess)
@@ -431,7 +432,7 @@ int xrdvi_tape_create(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     t->prob = prob;
     t->device = ctx->device;
     t->mem = mem;
-    t->st = carve_step(mem, P.ntiles, P.K, P.T, S, P.N);
+    t->st = carve_step(mem, P.ntiles, P.K, P.T, S, P.N, P.cutoff == 0.0);
     *out = t;
     return XRDVI_OK;
     API_GUARD_END
@@ -457,8 +458,8 @@ int xrdvi_profile(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     DeviceGuard g(ctx->device);
     const ProbDev &P = prob->P;
     int rc = XRDVI_OK;
-    if (!ensure_ws(ctx, step_bytes(P.ntiles, P.K, P.T, S, P.N), &rc)) return rc;
-    StepDev st = carve_step(ctx->ws, P.ntiles, P.K, P.T, S, P.N);
+    if (!ensure_ws(ctx, step_bytes(P.ntiles, P.K, P.T, S, P.N, P.cutoff == 0.0), &rc)) return rc;
+    StepDev st = carve_step(ctx->ws, P.ntiles, P.K, P.T, S, P.N, P.cutoff == 0.0);
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(launch_phi_consts(P, S, phi, st.pk, s), "phi constants");
     if (P.cutoff > 0.0)

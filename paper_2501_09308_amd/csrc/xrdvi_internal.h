@@ -41,10 +41,12 @@ void set_error(const std::string &msg);
 
 constexpr int kMaxSamples = 1024;
 
-// Bytes of per-step device state for (N, K, T, S), laid out by carve_step.
-size_t step_bytes(int ntiles, int K, int T, int S, int N);
+// Bytes of per-step device state for (N, K, T, S), laid out by carve_step;
+// the tile partial sums exist only for the dense (cutoff 0) path.
+size_t step_bytes(int ntiles, int K, int T, int S, int N, bool dense);
 // Carves StepDev buffers out of `base` (256-byte aligned pieces).
-StepDev carve_step(void *base, int ntiles, int K, int T, int S, int N);
+StepDev carve_step(void *base, int ntiles, int K, int T, int S, int N,
+                   bool dense);
 
 inline int num_tiles(int N) { return (N + kTile - 1) / kTile; }
 

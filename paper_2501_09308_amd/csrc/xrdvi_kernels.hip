@@ -172,10 +172,11 @@ hipError_t launch_fused(const ProbDev &P, const StepDev &st, bool grad,
             dim3 ga(P.K, st.S);
             k_adjoint_win<<<ga, kBlock, 0, stream>>>(P, st);
         }
-    } else if (grad) {
-        k_fused<false, true><<<g, kBlock, 0, stream>>>(P, st, f_out);
     } else {
-        k_fused<false, false><<<g, kBlock, 0, stream>>>(P, st, f_out);
+        StepDev sd = st;
+        sd.rres = nullptr;      // dense: the residual stays in LDS
+        if (grad) k_fused<false, true><<<g, kBlock, 0, stream>>>(P, sd, f_out);
+        else k_fused<false, false><<<g, kBlock, 0, stream>>>(P, sd, f_out);
     }
     return hipGetLastError();
 }
