@@ -56,6 +56,7 @@ __global__ __launch_bounds__(256) void kb_sample(const SlotDev *tab,
         if (!running(d)) continue;
         const int local = u - ps.pre[i];
         const int nkb = (d.P.K + kWave - 1) / kWave;
+        if (local / nkb >= d.st.S) continue;
         sample_block(d.P, d.st, d.loc, d.logscale, nullptr, d.seed,
                      (uint64_t)*d.step, local / nkb, local % nkb, nkb, sm);
         __syncthreads();
@@ -103,6 +104,7 @@ __global__ __launch_bounds__(kBlock) void kb_fused(const SlotDev *tab,
         if (!running(d)) continue;
         const int local = u - ps.pre[i];
         const int t = local % d.P.ntiles, s = local / d.P.ntiles;
+        if (s >= d.st.S) continue;
         if (d.P.cutoff > 0.0) fused_tile<true, false>(d.P, d.st, t, s, nullptr, sm);
         else fused_tile<false, true>(d.P, d.st, t, s, nullptr, sm);
         __syncthreads();
@@ -120,6 +122,7 @@ __global__ __launch_bounds__(kBlock) void kb_adjoint(const SlotDev *tab,
         const SlotDev &d = tab[ps.slot[i]];
         if (!running(d)) continue;
         const int local = u - ps.pre[i];
+        if (local / d.P.K >= d.st.S || d.P.cutoff == 0.0) continue;
         adjoint_phase(d.P, d.st, local / d.P.K, local % d.P.K, red);
         __syncthreads();
     }
@@ -151,6 +154,7 @@ __global__ __launch_bounds__(256) void kb_grad_adam(const SlotDev *tab,
         const int i = find_slot(ps, u);
         const SlotDev &d = tab[ps.slot[i]];
         if (!running(d)) continue;
+        if (u - ps.pre[i] >= d.P.K) continue;
         AdamArgs a;
         a.m1_loc = d.m1_loc; a.m2_loc = d.m2_loc;
         a.m1_ls = d.m1_ls; a.m2_ls = d.m2_ls;

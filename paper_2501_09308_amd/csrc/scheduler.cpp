@@ -156,6 +156,7 @@ void Scheduler::complete(Job *j, int state) {
     if (j->slot >= 0) slot_used_[j->slot] = 0;
     j->slot = -1;
     j->active = false;
+    changed_ = true;
     j->state = state;
     j->t_done = now();
     active_.erase(std::remove(active_.begin(), active_.end(), j), active_.end());
@@ -196,6 +197,7 @@ void Scheduler::loop() {
             j->arena_off = off;
             j->t_admit = now();
             j->active = true;
+            changed_ = true;
             active_.push_back(j);
             lk.unlock();
             const int rc = ex_->start(*j, j->slot, off);
@@ -212,8 +214,10 @@ void Scheduler::loop() {
             continue;
         }
         std::vector<Job *> batch(active_);
+        const bool changed = changed_;
+        changed_ = false;
         lk.unlock();
-        const int rc = ex_->run(batch, steps_per_run_);
+        const int rc = ex_->run(batch, steps_per_run_, changed);
         lk.lock();
         for (Job *j : batch) {
             if (rc != kOk) {

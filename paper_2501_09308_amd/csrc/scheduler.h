@@ -70,8 +70,12 @@ class Executor {
     // Upload and initialise job j into `slot` at arena offset `off`.
     virtual int start(Job &j, int slot, size_t off) = 0;
     // Advance every job of `active` by up to `steps` optimisation steps and
-    // update their steps_done.  A non-zero return fails all of them.
-    virtual int run(const std::vector<Job *> &active, int steps) = 0;
+    // update their steps_done.  `changed` is set whenever the resident set
+    // differs from the previous call (a job admitted, finished or dropped;
+    // a slot may now hold another job of another shape).  A non-zero
+    // return fails all of them.
+    virtual int run(const std::vector<Job *> &active, int steps,
+                    bool changed) = 0;
     // Copy the results of a finished job to its caller buffers and set
     // final_elbo; a negative return marks the job failed.
     virtual int finish(Job &j) = 0;
@@ -116,6 +120,7 @@ class Scheduler {
     std::map<uint64_t, std::unique_ptr<Job>> jobs_;
     uint64_t next_ticket_ = 1;
     bool stop_ = false;
+    bool changed_ = true;
     std::thread worker_;
     double t0_;
 };

@@ -138,19 +138,21 @@ class GpuExecutor : public Executor {
         return XRDVI_OK;
     }
 
-    int run(const std::vector<Job *> &active, int steps) override {
+    int run(const std::vector<Job *> &active, int steps, bool changed) override {
         (void)hipSetDevice(device_);
-        std::vector<int> members;
-        for (const Job *j : active) members.push_back(j->slot);
+        // membership = (slot, ticket): a slot re-used by another analysis
+        // changes its shape and therefore its work units
+        std::vector<std::pair<int, uint64_t>> members;
+        for (const Job *j : active) members.emplace_back(j->slot, j->ticket);
         std::sort(members.begin(), members.end());
         hipError_t e = hipSuccess;
-        if (members != members_) {
+        if (changed || members != members_) {
             members_ = members;
             SchedDev &h = *h_sch_;
             h.n = (int)members.size();
             for (int kind = 0; kind < kKinds; ++kind) h.pre[kind][0] = 0;
             for (int i = 0; i < h.n; ++i) {
-                const int sl = members[i];
+                const int sl = members[i].first;
                 h.slot[i] = sl;
                 int units[kKinds];
                 batch_units(h_tab_[sl].P, h_tab_[sl].st.S, units);
@@ -237,7 +239,7 @@ class GpuExecutor : public Executor {
     SchedDev *d_sch_ = nullptr;
     int *d_steps_ = nullptr;
     int h_steps_[kMaxSlots] = {};
-    std::vector<int> members_;
+    std::vector<std::pair<int, uint64_t>> members_;
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t gexec_ = nullptr;
 };

@@ -28,9 +28,18 @@ class FakeExecutor : public Executor {
         used_slots_ = std::max(used_slots_, slot + 1);
         return 0;
     }
-    int run(const std::vector<Job *> &active, int steps) override {
+    int run(const std::vector<Job *> &active, int steps, bool changed) override {
         max_active_ = std::max<int>(max_active_, (int)active.size());
         ++runs_;
+        // the resident set as (slot, ticket): any difference from the last
+        // run must be announced, or the executor would keep stale work
+        // prefixes for a slot now holding another analysis
+        std::vector<std::pair<int, uint64_t>> members;
+        for (const Job *j : active) members.emplace_back(j->slot, j->ticket);
+        std::sort(members.begin(), members.end());
+        if (members != last_ && !changed) ++missed_changes_;
+        if (changed) ++changed_runs_;
+        last_ = members;
         for (Job *j : active) j->steps_done = std::min(j->steps, j->steps_done + steps);
         if (sleep_us_) std::this_thread::sleep_for(std::chrono::microseconds(sleep_us_));
         return 0;
@@ -45,6 +54,8 @@ class FakeExecutor : public Executor {
     }
     void release(Job &) override {}
     int max_active_ = 0, runs_ = 0, used_slots_ = 0;
+    int missed_changes_ = 0, changed_runs_ = 0;
+    std::vector<std::pair<int, uint64_t>> last_;
 
   private:
     int sleep_us_;
@@ -98,6 +109,12 @@ void fake_stats(void *h, int *max_active, int *runs, int *used_slots) {
     *max_active = f->ex->max_active_;
     *runs = f->ex->runs_;
     *used_slots = f->ex->used_slots_;
+}
+
+void fake_changes(void *h, int *missed, int *changed_runs) {
+    auto *f = static_cast<Fake *>(h);
+    *missed = f->ex->missed_changes_;
+    *changed_runs = f->ex->changed_runs_;
 }
 
 void fake_destroy(void *h) {

@@ -17,7 +17,8 @@ class StepExecutor : public Executor {
   public:
     size_t footprint(const Job &j) const override { return (size_t)j.K * 512; }
     int start(Job &j, int, size_t) override { j.steps_done = 0; return 0; }
-    int run(const std::vector<Job *> &a, int steps) override {
+    int run(const std::vector<Job *> &a, int steps, bool changed) override {
+        (void)changed;
         for (Job *j : a) j->steps_done = std::min(j->steps, j->steps_done + steps);
         std::this_thread::sleep_for(std::chrono::microseconds(50));
         return 0;

@@ -159,3 +159,25 @@ def test_server_errors_and_cancel():
     with pytest.raises(X.XrdviError):
         srv.poll(ok)
     srv.close()
+
+
+def test_slot_reuse_by_analyses_of_other_shapes():
+    """One slot, several queued analyses of different K, N and S: each is
+    admitted into the slot its predecessor left, and must still match its
+    one-at-a-time run (regression: the batched work prefix must follow the
+    slot's new occupant)."""
+    ctx = context()
+    shapes = [(3000, 30, 10, 8), (1200, 6, 8, 2), (2200, 12, 15, 4),
+              (900, 4, 5, 3)]
+    cases = [(small_case(700 + i, N=N, K=K, M=M), S)
+             for i, (N, K, M, S) in enumerate(shapes)]
+    srv = X.Server(max_slots=1, steps_per_launch=2, arena_bytes=1 << 28)
+    tickets = [srv.submit(p, y, S, 6, 50 + i) for i, ((p, y), S) in enumerate(cases)]
+    res = wait_all(srv, tickets)
+    srv.close()
+    for i, ((p, y), S) in enumerate(cases):
+        rc, info, out = res[tickets[i]]
+        assert rc == X.XRDVI_OK
+        ref = X.xrdvi_plain_run(ctx, p, y, S, 6, 50 + i)
+        for k in ("loc", "logscale", "trace"):
+            np.testing.assert_allclose(out[k], ref[k], rtol=1e-12, atol=1e-12)

@@ -35,6 +35,7 @@ def lib():
     l.fake_cancel.argtypes = [C.c_void_p, C.c_uint64]
     l.fake_stats.argtypes = [C.c_void_p] + [C.POINTER(C.c_int)] * 3
     l.fake_destroy.argtypes = [C.c_void_p]
+    l.fake_changes.argtypes = [C.c_void_p] + [C.POINTER(C.c_int)] * 2
     return l
 
 
@@ -96,6 +97,30 @@ def test_all_complete_with_routed_outputs_and_batching(lib):
     max_active, runs, used = f.stats()
     assert max_active == 4          # continuous batching up to the slot limit
     assert used <= 4                 # slots are reused
+    f.close()
+
+
+def test_slot_reuse_is_announced_as_a_membership_change(lib):
+    # one slot: every job runs in slot 0, so the slot-id set never changes;
+    # the scheduler must still flag each new resident (regression: a stale
+    # per-slot work prefix made batched kernels index past a smaller job)
+    f = Fake(lib, slots=1, steps=4, sleep_us=100)
+    tickets = [f.submit(K=3 + i, N=50 + 10 * i, steps=8)[1] for i in range(6)]
+    f.wait(tickets)
+    missed, changed = C.c_int(), C.c_int()
+    lib.fake_changes(f.h, C.byref(missed), C.byref(changed))
+    assert missed.value == 0
+    assert changed.value >= 6
+    f.close()
+
+
+def test_membership_changes_announced_under_churn(lib):
+    f = Fake(lib, slots=5, steps=3, sleep_us=100)
+    tickets = [f.submit(K=2 + i % 7, steps=3 + (i * 7) % 11)[1] for i in range(40)]
+    f.wait(tickets)
+    missed, changed = C.c_int(), C.c_int()
+    lib.fake_changes(f.h, C.byref(missed), C.byref(changed))
+    assert missed.value == 0
     f.close()
 
 
