@@ -355,6 +355,221 @@ int oracle_elbo(int N, int K, const double *x, const double *y,
     return 0;
 }
 
+/* ---- asymmetric peaks (Appendix A.2, asymmetry factor A(x; alpha)) ----- */
+/*
+ * Reading of the lost equation that uses A: the peak keeps width w below
+ * rho and takes width alpha w above it (A = alpha for x >= rho, 1 below),
+ * with one common height at rho and the normalisation 2 / (1 + alpha), so
+ * every peak keeps unit area:
+ *   V(d) = 2/(1+alpha) * (w_A / w) * [(1-r) G(d; w_A) + r L(d; w_A)],
+ *   w_A = w A(d).
+ * alpha = 1 gives the symmetric pseudo-Voigt.  The window of a peak spans
+ * rho - c w .. rho + (c w) alpha.  Latents per phase: (h, mu, w, r, alpha),
+ * alpha = exp(z_alpha) with prior N(alpha_mean, alpha_sd) (Appendix B.2).
+ */
+static double voigt_asym(double d, double w, double r, double alpha)
+{
+    const double wA = (d >= 0.0) ? alpha * w : w;
+    return 2.0 / (1.0 + alpha) * (wA / w)
+         * ((1.0 - r) * gauss_fwhm(d, wA) + r * lorentz_fwhm(d, wA));
+}
+
+static int in_window_asym(double x, double rho, double w, double alpha,
+                          double c)
+{
+    if (c == 0.0) return 1;
+    const double hw = c * w;
+    const double lo = rho - hw;
+    const double hwr = hw * alpha;
+    const double hi = rho + hwr;
+    return (lo <= x) && (x <= hi);
+}
+
+/* f[s][i] with phi[s][5][K] rows (h, mu, w, r, alpha). */
+int oracle_profile_asym(int N, int K, const double *x, const double *B,
+                        const int *peak_off, const double *p,
+                        const double *I, double c, int S, const double *phi,
+                        double *f)
+{
+    if (N < 1 || K < 1 || S < 1) return -1;
+    #pragma omp parallel for schedule(dynamic)
+    for (int s = 0; s < S; ++s) {
+        const double *h = phi + (size_t)s * 5 * K;
+        const double *mu = h + K, *w = h + 2 * K, *r = h + 3 * K,
+                     *al = h + 4 * K;
+        double *fs = f + (size_t)s * N;
+        for (int i = 0; i < N; ++i) fs[i] = B[i];
+        for (int k = 0; k < K; ++k) {
+            for (int m = peak_off[k]; m < peak_off[k + 1]; ++m) {
+                const double rho = p[m] + mu[k];
+                for (int i = 0; i < N; ++i) {
+                    if (!in_window_asym(x[i], rho, w[k], al[k], c)) continue;
+                    fs[i] += h[k] * I[m] * voigt_asym(x[i] - rho, w[k], r[k],
+                                                      al[k]);
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+int oracle_windows_asym(int N, int K, const double *x, const int *peak_off,
+                        const double *p, double c, int S, const double *phi,
+                        int *lo, int *hi)
+{
+    const int T = peak_off[K];
+    for (int s = 0; s < S; ++s) {
+        const double *mu = phi + (size_t)s * 5 * K + K;
+        const double *w = mu + K, *al = mu + 3 * K;
+        for (int k = 0; k < K; ++k) {
+            for (int m = peak_off[k]; m < peak_off[k + 1]; ++m) {
+                const double rho = p[m] + mu[k];
+                int first = -1, last = -1;
+                for (int i = 0; i < N; ++i) {
+                    if (in_window_asym(x[i], rho, w[k], al[k], c)) {
+                        if (first < 0) first = i;
+                        last = i;
+                    }
+                }
+                int *l = lo + (size_t)s * T + m, *u = hi + (size_t)s * T + m;
+                if (first < 0) {
+                    int ins = 0;
+                    while (ins < N && x[ins] < rho) ++ins;
+                    *l = ins; *u = ins;
+                } else {
+                    *l = first; *u = last + 1;
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+/*
+ * ELBO of the asymmetric model (P = 5K coordinates) and its gradient; the
+ * same estimator as oracle_elbo with alpha ~ N(alpha_mean, alpha_sd),
+ * alpha = exp(z_alpha).  loc, logscale: [5][K]; eps: [S][5][K].
+ */
+int oracle_elbo_asym(int N, int K, const double *x, const double *y,
+                     const double *B, const int *peak_off, const double *p,
+                     const double *I, double c, double lambda, double mu_sd,
+                     double w_shape, double w_rate, double alpha_mean,
+                     double alpha_sd, int S, const double *loc,
+                     const double *logscale, const double *eps, double *elbo,
+                     double *loglik, double *grad_loc, double *grad_logscale)
+{
+    if (N < 1 || K < 1 || S < 1) return -1;
+    prob_t P = {N, K, x, y, B, peak_off, p, I, c, lambda, mu_sd, w_shape,
+                w_rate};
+    if (P.lambda == 0.0) {
+        const double ymax = max_signal(&P);
+        if (!(ymax > 0.0)) return -2;
+        P.lambda = 1.0 / ymax;
+    }
+    const int D = 5 * K;
+    double *phi = malloc(sizeof(double) * (size_t)S * D);
+    double *lpj = malloc(sizeof(double) * (size_t)S);
+    double *ll = malloc(sizeof(double) * (size_t)S);
+    double *gz = malloc(sizeof(double) * (size_t)S * D);
+    double *f = malloc(sizeof(double) * (size_t)S * N);
+    if (!phi || !lpj || !ll || !gz || !f) {
+        free(phi); free(lpj); free(ll); free(gz); free(f);
+        return -3;
+    }
+    for (int s = 0; s < S; ++s) {
+        double acc = 0.0;
+        for (int k = 0; k < K; ++k) {
+            double zz[5];
+            for (int t = 0; t < 5; ++t) {
+                const int j = t * K + k;
+                const double sd = exp(logscale[j]);
+                const double step = sd * eps[(size_t)s * D + j];
+                zz[t] = loc[j] + step;
+            }
+            double h, mu, w, r, lj;
+            transform(zz[0], zz[1], zz[2], zz[3], &h, &mu, &w, &r, &lj);
+            const double al = exp(zz[4]);
+            double *ph = phi + (size_t)s * D;
+            ph[k] = h; ph[K + k] = mu; ph[2 * K + k] = w; ph[3 * K + k] = r;
+            ph[4 * K + k] = al;
+            acc += oracle_log_prior(h, mu, w, r, P.lambda, mu_sd, w_shape,
+                                    w_rate)
+                 + log_normal_pdf(al, alpha_mean, alpha_sd) + lj + zz[4];
+        }
+        lpj[s] = acc;
+    }
+    oracle_profile_asym(N, K, x, B, peak_off, p, I, c, S, phi, f);
+    oracle_loglik(N, S, y, f, ll);
+    double mean = 0.0;
+    for (int s = 0; s < S; ++s) mean += ll[s] + lpj[s];
+    mean /= (double)S;
+    double ent = 0.0;
+    for (int j = 0; j < D; ++j) ent += logscale[j];
+    ent += 0.5 * (double)D * (1.0 + log(2.0 * M_PI));
+    *elbo = mean + ent;
+    if (loglik) for (int s = 0; s < S; ++s) loglik[s] = ll[s];
+
+    if (grad_loc && grad_logscale) {
+        const double ln2 = log(2.0);
+        const double cG = 2.0 * sqrt(ln2 / M_PI), cL = 2.0 / M_PI;
+        #pragma omp parallel for collapse(2) schedule(dynamic)
+        for (int s = 0; s < S; ++s) {
+            for (int k = 0; k < K; ++k) {
+                const double *ph = phi + (size_t)s * D;
+                const double h = ph[k], mu = ph[K + k], w = ph[2 * K + k],
+                             r = ph[3 * K + k], al = ph[4 * K + k];
+                const double Na = 2.0 / (1.0 + al);
+                const double *fs = f + (size_t)s * N;
+                double gh = 0.0, gmu = 0.0, gw = 0.0, gr = 0.0, ga = 0.0;
+                for (int m = peak_off[k]; m < peak_off[k + 1]; ++m) {
+                    const double rho = p[m] + mu;
+                    for (int i = 0; i < N; ++i) {
+                        if (!in_window_asym(x[i], rho, w, al, c)) continue;
+                        const double rres = y[i] / fs[i] - 1.0;
+                        const double d = x[i] - rho;
+                        const int right = d >= 0.0;
+                        const double wA = right ? al * w : w;
+                        const double q = d / wA;
+                        /* V = Na v(q) / w with v = (1-r) cG g + r cL lam */
+                        const double g = exp(-4.0 * ln2 * q * q);
+                        const double lam = 1.0 / (1.0 + 4.0 * q * q);
+                        const double v = (1.0 - r) * cG * g + r * cL * lam;
+                        const double dv = (1.0 - r) * cG * (-8.0 * ln2 * q) * g
+                                        + r * cL * (-8.0 * q) * lam * lam;
+                        const double a = rres * I[m];
+                        gh += a * Na * v / w;
+                        gmu += a * h * Na * dv * (-1.0 / wA) / w;
+                        gw += a * h * (-Na / (w * w)) * (v + q * dv);
+                        gr += a * h * Na / w * (cL * lam - cG * g);
+                        ga += a * h * (-Na / (1.0 + al) * v / w
+                                       + (right ? Na / w * dv * (-q / al) : 0.0));
+                    }
+                }
+                double *gzz = gz + (size_t)s * D;
+                gzz[k] = h * gh - P.lambda * h + 1.0;
+                gzz[K + k] = gmu - mu / (mu_sd * mu_sd);
+                gzz[2 * K + k] = w * gw + (w_shape - 1.0) - w_rate * w + 1.0;
+                gzz[3 * K + k] = r * (1.0 - r) * gr + 1.0 - 2.0 * r;
+                gzz[4 * K + k] = al * ga
+                               - al * (al - alpha_mean) / (alpha_sd * alpha_sd)
+                               + 1.0;
+            }
+        }
+        for (int j = 0; j < D; ++j) {
+            double gm = 0.0, go = 0.0;
+            const double sd = exp(logscale[j]);
+            for (int s = 0; s < S; ++s) {
+                gm += gz[(size_t)s * D + j];
+                go += gz[(size_t)s * D + j] * eps[(size_t)s * D + j] * sd;
+            }
+            grad_loc[j] = gm / (double)S;
+            grad_logscale[j] = go / (double)S + 1.0;
+        }
+    }
+    free(phi); free(lpj); free(ll); free(gz); free(f);
+    return 0;
+}
+
 /* ---- Adam (Kingma & Ba 2015) on the maximisation of the ELBO ----------- */
 
 /* One ascent step on theta with gradient g; m1, m2 are the moment

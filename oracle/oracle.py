@@ -57,6 +57,11 @@ def load():
     lib.oracle_eps_philox.argtypes = [C.c_int, C.c_int, C.c_uint64,
                                       C.c_uint64, _D]
     lib.oracle_num_threads.restype = C.c_int
+    lib.oracle_profile_asym.argtypes = lib.oracle_profile.argtypes
+    lib.oracle_windows_asym.argtypes = lib.oracle_windows.argtypes
+    lib.oracle_elbo_asym.argtypes = ([C.c_int, C.c_int, _D, _D, _D, _I, _D, _D]
+                                     + [C.c_double] * 7
+                                     + [C.c_int, _D, _D, _D, _D, _D, _D, _D])
     _lib = lib
     return lib
 
@@ -171,6 +176,64 @@ def eps_philox(S, K, seed, step):
     lib.oracle_eps_philox(S, K, C.c_uint64(seed), C.c_uint64(step),
                           out.ctypes.data_as(_D))
     return out
+
+
+def profile_asym(x, B, peak_off, p, I, c, phi):
+    """f[S][N] for constrained phi[S][5][K] (h, mu, w, r, alpha)."""
+    lib = load()
+    phi = np.asarray(phi, dtype=np.float64)
+    if phi.ndim == 2:
+        phi = phi[None]
+    S, _, K = phi.shape
+    f = np.empty((S, len(x)))
+    keep = [_d(x), _d(B), _i(peak_off), _d(p), _d(I), _d(phi)]
+    rc = lib.oracle_profile_asym(len(x), K, keep[0][1], keep[1][1], keep[2][1],
+                                 keep[3][1], keep[4][1], float(c), S,
+                                 keep[5][1], f.ctypes.data_as(_D))
+    assert rc == 0, rc
+    return f
+
+
+def windows_asym(x, peak_off, p, c, phi):
+    lib = load()
+    phi = np.asarray(phi, dtype=np.float64)
+    if phi.ndim == 2:
+        phi = phi[None]
+    S, _, K = phi.shape
+    T = int(peak_off[-1])
+    lo = np.empty((S, T), dtype=np.int32)
+    hi = np.empty((S, T), dtype=np.int32)
+    keep = [_d(x), _i(peak_off), _d(p), _d(phi)]
+    lib.oracle_windows_asym(len(x), K, keep[0][1], keep[1][1], keep[2][1],
+                            float(c), S, keep[3][1], lo.ctypes.data_as(_I),
+                            hi.ctypes.data_as(_I))
+    return lo, hi
+
+
+def elbo_asym(prob, y, loc, logscale, eps, *, lam=0.0, mu_sd=0.03,
+              w_shape=3.0, w_rate=100.0, alpha_mean=1.0, alpha_sd=0.2,
+              grad=True, c=None):
+    """Asymmetric model: loc, logscale [5][K], eps [S][5][K]."""
+    lib = load()
+    eps = np.ascontiguousarray(eps, dtype=np.float64)
+    S, K = eps.shape[0], prob.K
+    cut = prob.cutoff if c is None else c
+    gl = np.empty((5, K)); gs = np.empty((5, K)); ll = np.empty(S)
+    out = C.c_double(0.0)
+    keep = [_d(prob.x), _d(y), _d(prob.bg), _i(prob.peak_off),
+            _d(prob.peak_pos), _d(prob.peak_int), _d(loc), _d(logscale),
+            _d(eps)]
+    rc = lib.oracle_elbo_asym(prob.N, K, keep[0][1], keep[1][1], keep[2][1],
+                              keep[3][1], keep[4][1], keep[5][1], float(cut),
+                              float(lam), float(mu_sd), float(w_shape),
+                              float(w_rate), float(alpha_mean),
+                              float(alpha_sd), S, keep[6][1], keep[7][1],
+                              keep[8][1], C.byref(out), ll.ctypes.data_as(_D),
+                              gl.ctypes.data_as(_D) if grad else None,
+                              gs.ctypes.data_as(_D) if grad else None)
+    if rc != 0:
+        raise ValueError(f"oracle_elbo_asym failed: {rc}")
+    return out.value, ll, (gl if grad else None), (gs if grad else None)
 
 
 def num_threads():
