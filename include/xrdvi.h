@@ -13,8 +13,18 @@
  * rate), r ~ U(0,1).  The posterior is approximated by a mean-field
  * Gaussian q (Sec. 3.2) over unconstrained z with h = exp(z_h), mu = z_mu,
  * w = exp(z_w), r = logistic(z_r); its parameters are loc (means) and
- * logscale (log standard deviations), each laid out [4][K] with rows
- * (h, mu, w, r).
+ * logscale (log standard deviations), each laid out [D][K] with rows
+ * (h, mu, w, r), D = 4.
+ *
+ * Asymmetric peaks (Appendix A.2, asymmetry factor A(x; alpha), which is
+ * alpha at and above the peak centre rho and 1 below it; prior
+ * alpha ~ N(1, 0.2), Appendix B.2): a problem created with `asymmetric`
+ * set gives each phase a fifth latent alpha = exp(z_alpha) (D = 5, row 4)
+ * and evaluates
+ *     V_alpha(x) = 2/(1 + alpha) * [(1-r) G + r L](x; rho, A w) * A
+ * i.e. the pseudo-Voigt with full width w below rho and alpha w above,
+ * scaled to unit area (continuous at rho; alpha = 1 gives V).  Every array
+ * documented below as [..][D][K] then has five rows.
  *
  * Conventions for every call:
  *  - Return value: XRDVI_OK (0) or a negative error code; a message for the
@@ -68,6 +78,8 @@ typedef struct {
     double mu_sd;     /* sd of the normal prior on the shift, 0.03 deg    */
     double w_shape;   /* gamma prior on the width: shape 3 ...            */
     double w_rate;    /* ... and rate 100 (mean 0.03 deg)                  */
+    double alpha_mean;  /* normal prior on the asymmetry alpha: mean 1 ...  */
+    double alpha_sd;    /* ... and sd 0.2 (used only with `asymmetric`)     */
 } xrdvi_prior;
 
 /*
@@ -82,8 +94,10 @@ typedef struct {
  *   peak_pos[T] peak positions p_m (deg), finite; T = peak_off[K]
  *   peak_int[T] relative intensities I_m in [0, 1]
  *   cutoff      c >= 0: peak m of phase k contributes only at points with
- *               rho - c w <= x_i <= rho + c w (rho = p_m + mu_k, w = FWHM);
+ *               rho - c w <= x_i <= rho + c w (rho = p_m + mu_k, w = FWHM;
+ *               the upper bound is rho + (c w) alpha for asymmetric peaks);
  *               c = 0 keeps every point (the paper's dense sum)
+ *   asymmetric  0: symmetric peaks (D = 4); 1: asymmetric peaks (D = 5)
  */
 typedef struct {
     int32_t N, K;
@@ -92,6 +106,7 @@ typedef struct {
     const double *peak_pos, *peak_int;
     double cutoff;
     xrdvi_prior prior;
+    int32_t asymmetric;
 } xrdvi_problem_desc;
 
 XRDVI_API const char *xrdvi_last_error(void);
@@ -129,8 +144,9 @@ XRDVI_API int xrdvi_tape_destroy(xrdvi_tape *tape);
 /*
  * Profile f[s][i] = B_i + sum_k h_k C_k(x_i) (Appendix A.2, signal and
  * profile equations) at given constrained latents.
- *   phi    device double [S][4][K], rows (h, mu, w, r); requires h >= 0,
- *          w > 0, 0 <= r <= 1 (other values give unspecified output)
+ *   phi    device double [S][D][K], rows (h, mu, w, r[, alpha]); requires
+ *          h >= 0, w > 0, 0 <= r <= 1, alpha > 0 (other values give
+ *          unspecified output)
  *   f_out  device float [S][N]
  * Peak values are evaluated in FP32 on tile-relative coordinates and summed
  * onto the FP64 background.  The first call at a larger S grows the
@@ -142,11 +158,11 @@ XRDVI_API int xrdvi_profile(xrdvi_ctx *ctx, const xrdvi_problem *prob,
 
 /*
  * Window plan: for each sample s and peak m (caller's peak order),
- * lo[s][m] = first grid index inside [rho - c w, rho + c w] and hi[s][m] =
- * one past the last (lo = hi when empty), with rho = p_m + mu and the bounds
- * formed in FP64 by single rounded operations.  With c = 0 every window is
- * [0, N).
- *   phi     device double [S][4][K]
+ * lo[s][m] = first grid index inside [rho - c w, rho + c w] (upper bound
+ * rho + (c w) alpha for asymmetric peaks) and hi[s][m] = one past the last
+ * (lo = hi when empty), with rho = p_m + mu and the bounds formed in FP64 by
+ * single rounded operations.  With c = 0 every window is [0, N).
+ *   phi     device double [S][D][K]
  *   lo, hi  device int32 [S][T]
  */
 XRDVI_API int xrdvi_window_plan(xrdvi_ctx *ctx, const xrdvi_problem *prob,
@@ -158,9 +174,9 @@ XRDVI_API int xrdvi_window_plan(xrdvi_ctx *ctx, const xrdvi_problem *prob,
  * s < S, evaluates the profile, the Poisson log-likelihood (Appendix A.2)
  * and the estimate
  *   L = (1/S) sum_s [ln p(Y|phi_s) + ln p(phi_s) + ln|J(z_s)|]
- *       + sum_j logscale_j + 2K (1 + ln 2 pi).
- *   loc, logscale  device double [4][K]
- *   eps            device double [S][4][K] standard-normal noise, or NULL to
+ *       + sum_j logscale_j + (D K / 2) (1 + ln 2 pi).
+ *   loc, logscale  device double [D][K]
+ *   eps            device double [S][D][K] standard-normal noise, or NULL to
  *                  draw it on the device from Philox4x32-10 keyed by
  *                  (seed, step) with Box-Muller (counter (j/4, s, step))
  *   need_grad      non-zero: also run the recomputing adjoint so that
@@ -185,7 +201,7 @@ XRDVI_API int xrdvi_elbo_fwd(xrdvi_ctx *ctx, const xrdvi_problem *prob,
  * *grad_scale_dev when that device pointer is non-NULL (an upstream
  * gradient that stays on the device).  Window edges are held fixed (the
  * estimate is piecewise smooth in the parameters when c > 0).
- *   grad_loc, grad_logscale  device double [4][K]
+ *   grad_loc, grad_logscale  device double [D][K]
  */
 XRDVI_API int xrdvi_elbo_bwd(xrdvi_ctx *ctx, const xrdvi_tape *tape,
                              double grad_scale, const double *grad_scale_dev,
@@ -222,13 +238,13 @@ typedef struct {
     int32_t steps;                  /* optimisation steps, >= 1              */
     uint64_t seed;                  /* noise key                             */
     double lr;                      /* Adam step size; 0 selects 1e-2        */
-    const double *init_loc;         /* host [4][K] or NULL: m_h = ln(0.01 /
+    const double *init_loc;         /* host [D][K] or NULL: m_h = ln(0.01 /
                                        lambda), m_mu = 0, m_w = ln 0.1,
-                                       m_r = 0                               */
-    const double *init_logscale;    /* host [4][K] or NULL: ln 0.1           */
-    double *out_loc;                /* host [4][K] or NULL; written before
+                                       m_r = 0, m_alpha = 0                 */
+    const double *init_logscale;    /* host [D][K] or NULL: ln 0.1           */
+    double *out_loc;                /* host [D][K] or NULL; written before
                                        poll reports completion              */
-    double *out_logscale;           /* host [4][K] or NULL                   */
+    double *out_logscale;           /* host [D][K] or NULL                   */
     double *out_elbo_trace;         /* host [steps] or NULL: ELBO per step   */
 } xrdvi_request;
 
@@ -286,7 +302,7 @@ XRDVI_API int xrdvi_plain_run(xrdvi_ctx *ctx, const xrdvi_request *req,
 
 /*
  * Copies the constrained samples phi_s = T(z_s) drawn by the last
- * xrdvi_elbo_fwd on `tape` into phi_out (device double [S][4][K]), e.g. to
+ * xrdvi_elbo_fwd on `tape` into phi_out (device double [S][D][K]), e.g. to
  * inspect the approximate posterior or to count the peak-points of the
  * step with xrdvi_window_plan.
  */

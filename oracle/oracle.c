@@ -612,16 +612,15 @@ void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
 }
 
 /*
- * Standard-normal noise eps[s][j] (j = t*K + k) for one step of one
+ * Standard-normal noise eps[s][j], j < D (j = t*K + k), for one step of one
  * analysis: counter (j / 4, s, step low, step high), key (seed low, seed
  * high); the four 32-bit words map to uniforms u = (v + 0.5) / 2^32 and
  * the pairs (u0,u1), (u2,u3) to normals by the Box-Muller transform
  * (cos then sin).
  */
-void oracle_eps_philox(int S, int K, uint64_t seed, uint64_t step,
-                       double *eps)
+void oracle_eps_philox_n(int S, int D, uint64_t seed, uint64_t step,
+                         double *eps)
 {
-    const int D = 4 * K;
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     for (int s = 0; s < S; ++s) {
         for (int blk = 0; blk * 4 < D; ++blk) {
@@ -644,6 +643,13 @@ void oracle_eps_philox(int S, int K, uint64_t seed, uint64_t step,
             }
         }
     }
+}
+
+/* Noise of the symmetric model: D = 4 K numbers per sample. */
+void oracle_eps_philox(int S, int K, uint64_t seed, uint64_t step,
+                       double *eps)
+{
+    oracle_eps_philox_n(S, 4 * K, seed, step, eps);
 }
 
 int oracle_num_threads(void)

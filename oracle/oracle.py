@@ -56,6 +56,7 @@ def load():
                                          C.POINTER(C.c_uint32)]
     lib.oracle_eps_philox.argtypes = [C.c_int, C.c_int, C.c_uint64,
                                       C.c_uint64, _D]
+    lib.oracle_eps_philox_n.argtypes = lib.oracle_eps_philox.argtypes
     lib.oracle_num_threads.restype = C.c_int
     lib.oracle_profile_asym.argtypes = lib.oracle_profile.argtypes
     lib.oracle_windows_asym.argtypes = lib.oracle_windows.argtypes
@@ -170,11 +171,12 @@ def philox4x32_10(ctr, key):
     return [int(v) for v in o]
 
 
-def eps_philox(S, K, seed, step):
+def eps_philox(S, K, seed, step, D=4):
+    """Device noise [S][D][K] of (seed, step)."""
     lib = load()
-    out = np.empty((S, 4, K))
-    lib.oracle_eps_philox(S, K, C.c_uint64(seed), C.c_uint64(step),
-                          out.ctypes.data_as(_D))
+    out = np.empty((S, D, K))
+    lib.oracle_eps_philox_n(S, D * K, C.c_uint64(seed), C.c_uint64(step),
+                            out.ctypes.data_as(_D))
     return out
 
 

@@ -30,17 +30,39 @@ __device__ void load_prefix(const SchedDev *sch, int kind, PrefixSmem &ps) {
     __syncthreads();
 }
 
-// Resident index i with pre[i] <= u < pre[i + 1].
+__device__ __forceinline__ int uniform(int v) {
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Resident index i with pre[i] <= u < pre[i + 1] (u is block-uniform, so
+// the result is wave-uniform).
 __device__ int find_slot(const PrefixSmem &ps, int u) {
     int lo = 0, hi = ps.n;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (ps.pre[mid] <= u) lo = mid; else hi = mid;
     }
-    return lo;
+    return uniform(lo);
 }
 
-__device__ inline bool running(const SlotDev &d) { return *d.step < d.steps; }
+// Slot table entry of resident index i.  The table does not change while a
+// kernel runs, and the index is uniform, so the copy is made of scalar loads
+// and the problem and step descriptors stay in scalar registers, as the
+// arguments of the single-analysis kernels do.
+__device__ __forceinline__ const SlotDev &slot_entry(const SlotDev *tab,
+                                                     const PrefixSmem &ps,
+                                                     int i) {
+    return *(const SlotDev *)(as_const(tab) + uniform(ps.slot[i]));
+}
+
+// Unit index of u inside resident index i.
+__device__ __forceinline__ int local_unit(const PrefixSmem &ps, int i, int u) {
+    return uniform(u - ps.pre[i]);
+}
+
+__device__ inline bool running(const SlotDev &d) {
+    return uniform(*d.step) < d.steps;
+}
 
 }  // namespace
 
@@ -49,12 +71,12 @@ __global__ __launch_bounds__(256) void kb_sample(const SlotDev *tab,
     __shared__ PrefixSmem ps;
     __shared__ SampleSmem sm;
     load_prefix(sch, kSample, ps);
-    const int total = ps.pre[ps.n];
+    const int total = uniform(ps.pre[ps.n]);
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         const int i = find_slot(ps, u);
-        const SlotDev &d = tab[ps.slot[i]];
+        const SlotDev &d = slot_entry(tab, ps, i);
         if (!running(d)) continue;
-        const int local = u - ps.pre[i];
+        const int local = local_unit(ps, i, u);
         const int nkb = (d.P.K + kWave - 1) / kWave;
         if (local / nkb >= d.st.S) continue;
         sample_block(d.P, d.st, d.loc, d.logscale, nullptr, d.seed,
@@ -67,12 +89,12 @@ __global__ __launch_bounds__(256) void kb_windows(const SlotDev *tab,
                                                   const SchedDev *sch) {
     __shared__ PrefixSmem ps;
     load_prefix(sch, kWindows, ps);
-    const int total = ps.pre[ps.n];
+    const int total = uniform(ps.pre[ps.n]);
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         const int i = find_slot(ps, u);
-        const SlotDev &d = tab[ps.slot[i]];
+        const SlotDev &d = slot_entry(tab, ps, i);
         if (!running(d)) continue;
-        const size_t g = (size_t)(u - ps.pre[i]) * 256 + threadIdx.x;
+        const size_t g = (size_t)local_unit(ps, i, u) * 256 + threadIdx.x;
         if (g < (size_t)d.st.S * d.P.T)
             windows_elem(d.P, d.st.phi, d.st.lo, d.st.hi, nullptr, g);
     }
@@ -82,48 +104,50 @@ __global__ __launch_bounds__(256) void kb_plan(const SlotDev *tab,
                                                const SchedDev *sch) {
     __shared__ PrefixSmem ps;
     load_prefix(sch, kPlan, ps);
-    const int total = ps.pre[ps.n];
+    const int total = uniform(ps.pre[ps.n]);
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         const int i = find_slot(ps, u);
-        const SlotDev &d = tab[ps.slot[i]];
+        const SlotDev &d = slot_entry(tab, ps, i);
         if (!running(d)) continue;
-        const size_t g = (size_t)(u - ps.pre[i]) * 256 + threadIdx.x;
+        const size_t g = (size_t)local_unit(ps, i, u) * 256 + threadIdx.x;
         if (g < (size_t)d.st.S * d.P.ntiles * d.P.K) plan_elem(d.P, d.st, d.st.phi, g);
     }
 }
 
+template <bool WIN, bool ASYM>
 __global__ __launch_bounds__(kBlock) void kb_fused(const SlotDev *tab,
                                                    const SchedDev *sch) {
     __shared__ PrefixSmem ps;
     __shared__ FusedSmem sm;
-    load_prefix(sch, kFused, ps);
-    const int total = ps.pre[ps.n];
+    load_prefix(sch, fused_kind(WIN, ASYM), ps);
+    const int total = uniform(ps.pre[ps.n]);
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         const int i = find_slot(ps, u);
-        const SlotDev &d = tab[ps.slot[i]];
+        const SlotDev &d = slot_entry(tab, ps, i);
         if (!running(d)) continue;
-        const int local = u - ps.pre[i];
+        const int local = local_unit(ps, i, u);
         const int t = local % d.P.ntiles, s = local / d.P.ntiles;
         if (s >= d.st.S) continue;
-        if (d.P.cutoff > 0.0) fused_tile<true, false>(d.P, d.st, t, s, nullptr, sm);
-        else fused_tile<false, true>(d.P, d.st, t, s, nullptr, sm);
+        // windowed: forward only (the adjoint is peak-major); dense: fused
+        fused_tile<WIN, !WIN, ASYM>(d.P, d.st, t, s, nullptr, sm);
         __syncthreads();
     }
 }
 
+template <bool ASYM>
 __global__ __launch_bounds__(kBlock) void kb_adjoint(const SlotDev *tab,
                                                      const SchedDev *sch) {
     __shared__ PrefixSmem ps;
-    __shared__ double red[kWaves][6];
-    load_prefix(sch, kAdjoint, ps);
-    const int total = ps.pre[ps.n];
+    __shared__ double red[kWaves][12];
+    load_prefix(sch, ASYM ? kAdjointAsym : kAdjoint, ps);
+    const int total = uniform(ps.pre[ps.n]);
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         const int i = find_slot(ps, u);
-        const SlotDev &d = tab[ps.slot[i]];
+        const SlotDev &d = slot_entry(tab, ps, i);
         if (!running(d)) continue;
-        const int local = u - ps.pre[i];
+        const int local = local_unit(ps, i, u);
         if (local / d.P.K >= d.st.S || d.P.cutoff == 0.0) continue;
-        adjoint_phase(d.P, d.st, local / d.P.K, local % d.P.K, red);
+        adjoint_phase<ASYM>(d.P, d.st, local / d.P.K, local % d.P.K, red);
         __syncthreads();
     }
 }
@@ -133,10 +157,10 @@ __global__ __launch_bounds__(1024) void kb_elbo(const SlotDev *tab,
     __shared__ PrefixSmem ps;
     __shared__ ElboSmem sm;
     load_prefix(sch, kElbo, ps);
-    const int total = ps.pre[ps.n];
+    const int total = uniform(ps.pre[ps.n]);
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         const int i = find_slot(ps, u);
-        const SlotDev &d = tab[ps.slot[i]];
+        const SlotDev &d = slot_entry(tab, ps, i);
         if (!running(d)) continue;
         const double e = elbo_block(d.P, d.st, d.logscale, nullptr, sm);
         if (threadIdx.x == 0) d.trace[*d.step] = e;
@@ -149,18 +173,19 @@ __global__ __launch_bounds__(256) void kb_grad_adam(const SlotDev *tab,
     __shared__ PrefixSmem ps;
     __shared__ GradSmem sm;
     load_prefix(sch, kGrad, ps);
-    const int total = ps.pre[ps.n];
+    const int total = uniform(ps.pre[ps.n]);
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         const int i = find_slot(ps, u);
-        const SlotDev &d = tab[ps.slot[i]];
+        const SlotDev &d = slot_entry(tab, ps, i);
         if (!running(d)) continue;
-        if (u - ps.pre[i] >= d.P.K) continue;
+        const int k = local_unit(ps, i, u);
+        if (k >= d.P.K) continue;
         AdamArgs a;
         a.m1_loc = d.m1_loc; a.m2_loc = d.m2_loc;
         a.m1_ls = d.m1_ls; a.m2_ls = d.m2_ls;
         a.t = *d.step + 1;
         a.lr = d.lr; a.b1 = 0.9; a.b2 = 0.999; a.eps = 1e-8;
-        grad_block(d.P, d.st, u - ps.pre[i], 1.0, nullptr, nullptr, nullptr,
+        grad_block(d.P, d.st, k, 1.0, nullptr, nullptr, nullptr,
                    d.loc, d.logscale, &a, sm);
         __syncthreads();
     }
@@ -181,8 +206,12 @@ hipError_t launch_batch_step(const SlotDev *tab, const SchedDev *sch,
     kb_sample<<<kGridSmall, 256, 0, s>>>(tab, sch);
     kb_windows<<<kGridLarge, 256, 0, s>>>(tab, sch);
     kb_plan<<<kGridLarge, 256, 0, s>>>(tab, sch);
-    kb_fused<<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-    kb_adjoint<<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    kb_fused<true, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    kb_fused<false, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    kb_fused<true, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    kb_fused<false, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    kb_adjoint<false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    kb_adjoint<true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
     kb_elbo<<<kGridElbo, 1024, 0, s>>>(tab, sch);
     kb_grad_adam<<<kGridLarge, 256, 0, s>>>(tab, sch);
     kb_advance<<<1, 1024, 0, s>>>(tab, sch);

@@ -31,11 +31,13 @@ struct Job {
     std::vector<int> off;
     double cutoff = 0.0;
     double lambda_h = 0.0, mu_sd = 0.03, w_shape = 3.0, w_rate = 100.0;
+    int D = 4;                   // latent types per phase (5: asymmetric)
+    double alpha_mean = 1.0, alpha_sd = 0.2;
     // run
     int S = 1, steps = 1;
     uint64_t seed = 0;
     double lr = 1e-2;
-    std::vector<double> init_loc, init_logscale;   // [4K]
+    std::vector<double> init_loc, init_logscale;   // [D K]
     double *out_loc = nullptr, *out_logscale = nullptr, *out_trace = nullptr;
     // life cycle
     int state = 1;               // 1 pending (queued or active), 0 done, <0 error

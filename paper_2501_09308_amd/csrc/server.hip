@@ -40,6 +40,9 @@ xrdvi_problem_desc job_desc(const Job &j) {
     d.prior.mu_sd = j.mu_sd;
     d.prior.w_shape = j.w_shape;
     d.prior.w_rate = j.w_rate;
+    d.prior.alpha_mean = j.alpha_mean;
+    d.prior.alpha_sd = j.alpha_sd;
+    d.asymmetric = j.D == 5;
     return d;
 }
 
@@ -53,8 +56,9 @@ SlotLayout slot_layout(const Job &j) {
     const int T = j.off[j.K];
     L.prob = 0;
     L.step = a256(problem_bytes(j.N, j.K, T));
-    L.state = L.step + a256(step_bytes(num_tiles(j.N), j.K, T, j.S, j.N, j.cutoff == 0.0));
-    L.trace = L.state + a256(sizeof(double) * 6 * 4 * (size_t)j.K);
+    const StepShape sh{num_tiles(j.N), j.K, T, j.S, j.N, j.D, j.cutoff == 0.0};
+    L.state = L.step + a256(step_bytes(sh));
+    L.trace = L.state + a256(sizeof(double) * 6 * j.D * (size_t)j.K);
     L.total = L.trace + a256(sizeof(double) * (size_t)j.steps);
     return L;
 }
@@ -102,10 +106,9 @@ class GpuExecutor : public Executor {
         hipError_t e = upload_problem(desc, j.lambda_h, base + L.prob, d.P, nullptr,
                                       stream_);
         if (e != hipSuccess) return dev_fail(e, "upload");
-        d.st = carve_step(base + L.step, d.P.ntiles, j.K, d.P.T, j.S, j.N,
-                          j.cutoff == 0.0);
+        d.st = carve_step(base + L.step, step_shape(d.P, j.S));
         if (d.P.cutoff == 0.0) d.st.rres = nullptr;   // dense: no residual array
-        const size_t D = 4 * (size_t)j.K;
+        const size_t D = (size_t)j.D * j.K;
         double *state = (double *)(base + L.state);
         d.loc = state;
         d.logscale = state + D;
@@ -184,7 +187,7 @@ class GpuExecutor : public Executor {
     int finish(Job &j) override {
         (void)hipSetDevice(device_);
         const SlotDev &d = h_tab_[j.slot];
-        const size_t D = 4 * (size_t)j.K;
+        const size_t D = (size_t)j.D * j.K;
         std::vector<double> trace(j.steps);
         hipError_t e = hipMemcpyAsync(trace.data(), d.trace, sizeof(double) * j.steps,
                                       hipMemcpyDeviceToHost, stream_);
@@ -269,15 +272,18 @@ int make_job(const xrdvi_request *r, std::unique_ptr<Job> *out) {
     j->mu_sd = p.prior.mu_sd;
     j->w_shape = p.prior.w_shape;
     j->w_rate = p.prior.w_rate;
+    j->D = latent_types(p);
+    j->alpha_mean = p.prior.alpha_mean;
+    j->alpha_sd = p.prior.alpha_sd;
     j->S = r->S;
     j->steps = r->steps;
     j->seed = r->seed;
     j->lr = r->lr > 0.0 ? r->lr : 1e-2;
-    const size_t D = 4 * (size_t)p.K;
+    const size_t D = (size_t)j->D * p.K;
     if (r->init_loc) j->init_loc.assign(r->init_loc, r->init_loc + D);
     if (r->init_logscale) j->init_logscale.assign(r->init_logscale, r->init_logscale + D);
     // default initialisation: m_h = ln(0.01 / lambda), m_mu = 0,
-    // m_w = ln 0.1, m_r = 0, omega = ln 0.1
+    // m_w = ln 0.1, m_r = 0, m_alpha = 0, omega = ln 0.1
     if (j->init_loc.empty()) {
         j->init_loc.assign(D, 0.0);
         for (int k = 0; k < p.K; ++k) {
@@ -444,7 +450,7 @@ int xrdvi_plain_run(xrdvi_ctx *ctx, const xrdvi_request *req, xrdvi_status *st,
     xrdvi_tape *tape = nullptr;
     rc = xrdvi_problem_create(ctx, &desc, &prob);
     if (rc == XRDVI_OK) rc = xrdvi_tape_create(ctx, prob, j->S, &tape);
-    const size_t D = 4 * (size_t)j->K;
+    const size_t D = (size_t)j->D * j->K;
     double *mem = nullptr;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (rc == XRDVI_OK && hipMalloc(&mem, sizeof(double) * (8 * D + j->steps)) != hipSuccess)

@@ -47,46 +47,53 @@ void set_error(const std::string &msg) { g_err = msg; }
 
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-size_t step_bytes(int ntiles, int K, int T, int S, int N, bool dense) {
-    const size_t D = 4 * (size_t)K;
+size_t step_bytes(const StepShape &sh) {
+    const size_t S = sh.S, K = sh.K, D = (size_t)sh.D * K;
+    const size_t NS = num_sums(sh.D), nt = sh.ntiles;
     const size_t kb = (K + kWave - 1) / kWave;
+    const bool asym = sh.D == 5;
     size_t b = 0;
     b += align256(sizeof(double) * S * D);          // eps
     b += align256(sizeof(double) * S * D);          // phi
-    b += align256(sizeof(float4) * S * (size_t)K);  // pk
-    b += align256(sizeof(double) * S * (size_t)K);  // lpj
+    b += align256(sizeof(float4) * S * K);          // pk
+    b += align256(asym ? sizeof(float) * S * K : 4);  // pkr
+    b += align256(sizeof(double) * S * K);          // lpj
     b += align256(sizeof(double) * S * kb);         // lpb
-    b += 2 * align256(sizeof(int) * S * (size_t)std::max(T, 1));  // lo, hi
-    b += align256(sizeof(double) * S * (size_t)ntiles);           // llp
-    b += align256(dense ? sizeof(float) * 6 * (size_t)ntiles * K * S : 4);  // part
+    b += 2 * align256(sizeof(int) * S * (size_t)std::max(sh.T, 1));  // lo, hi
+    b += align256(sizeof(double) * S * nt);         // llp
+    b += align256(sh.dense ? sizeof(float) * NS * nt * K * S : 4);  // part
     b += align256(sizeof(double) * D);              // sd
-    b += align256(sizeof(int4) * S * (size_t)ntiles * K);         // rng
-    b += align256(sizeof(float) * S * (size_t)N);                 // rres
-    b += align256(sizeof(double) * 6 * (size_t)K * S);            // pw
+    b += align256(sizeof(int4) * S * nt * K);       // rng
+    b += align256(asym ? sizeof(int2) * S * nt * K : 4);  // rng2
+    b += align256(sizeof(float) * S * (size_t)sh.N);  // rres
+    b += align256(sizeof(double) * NS * K * S);     // pw
     return b;
 }
 
-StepDev carve_step(void *base, int ntiles, int K, int T, int S, int N,
-                   bool dense) {
+StepDev carve_step(void *base, const StepShape &sh) {
     char *p = static_cast<char *>(base);
-    const size_t D = 4 * (size_t)K;
+    const size_t S = sh.S, K = sh.K, D = (size_t)sh.D * K;
+    const size_t NS = num_sums(sh.D), nt = sh.ntiles;
     const size_t kb = (K + kWave - 1) / kWave;
+    const bool asym = sh.D == 5;
     auto take = [&](size_t bytes) { char *r = p; p += align256(bytes); return r; };
     StepDev st{};
-    st.S = S;
+    st.S = sh.S;
     st.eps = (double *)take(sizeof(double) * S * D);
     st.phi = (double *)take(sizeof(double) * S * D);
-    st.pk = (float4 *)take(sizeof(float4) * S * (size_t)K);
-    st.lpj = (double *)take(sizeof(double) * S * (size_t)K);
+    st.pk = (float4 *)take(sizeof(float4) * S * K);
+    st.pkr = (float *)take(asym ? sizeof(float) * S * K : 4);
+    st.lpj = (double *)take(sizeof(double) * S * K);
     st.lpb = (double *)take(sizeof(double) * S * kb);
-    st.lo = (int *)take(sizeof(int) * S * (size_t)std::max(T, 1));
-    st.hi = (int *)take(sizeof(int) * S * (size_t)std::max(T, 1));
-    st.llp = (double *)take(sizeof(double) * S * (size_t)ntiles);
-    st.part = (float *)take(dense ? sizeof(float) * 6 * (size_t)ntiles * K * S : 4);
+    st.lo = (int *)take(sizeof(int) * S * (size_t)std::max(sh.T, 1));
+    st.hi = (int *)take(sizeof(int) * S * (size_t)std::max(sh.T, 1));
+    st.llp = (double *)take(sizeof(double) * S * nt);
+    st.part = (float *)take(sh.dense ? sizeof(float) * NS * nt * K * S : 4);
     st.sd = (double *)take(sizeof(double) * D);
-    st.rng = (int4 *)take(sizeof(int4) * S * (size_t)ntiles * K);
-    st.rres = (float *)take(sizeof(float) * S * (size_t)N);
-    st.pw = (double *)take(sizeof(double) * 6 * (size_t)K * S);
+    st.rng = (int4 *)take(sizeof(int4) * S * nt * K);
+    st.rng2 = (int2 *)take(asym ? sizeof(int2) * S * nt * K : 4);
+    st.rres = (float *)take(sizeof(float) * S * (size_t)sh.N);
+    st.pw = (double *)take(sizeof(double) * NS * K * S);
     return st;
 }
 
@@ -150,6 +157,7 @@ hipError_t upload_problem(const xrdvi_problem_desc &d, double lambda,
     if (e != hipSuccess) return e;
     P = ProbDev{};
     P.N = N; P.K = K; P.T = T; P.ntiles = num_tiles(N);
+    P.D = latent_types(d);
     P.cutoff = d.cutoff;
     P.lambda = lambda;
     P.mu_sd = d.prior.mu_sd;
@@ -158,6 +166,11 @@ hipError_t upload_problem(const xrdvi_problem_desc &d, double lambda,
     P.c_h = std::log(lambda);
     P.c_mu = -std::log(d.prior.mu_sd) - 0.5 * std::log(2.0 * M_PI);
     P.c_w = d.prior.w_shape * std::log(d.prior.w_rate) - std::lgamma(d.prior.w_shape);
+    if (P.D == 5) {
+        P.a_mean = d.prior.alpha_mean;
+        P.a_sd = d.prior.alpha_sd;
+        P.c_a = -std::log(d.prior.alpha_sd) - 0.5 * std::log(2.0 * M_PI);
+    }
     P.x = (const double *)(base + L.x);
     P.y = (const double *)(base + L.y);
     P.bg = (const double *)(base + L.bg);
@@ -248,6 +261,12 @@ int validate_desc(const xrdvi_problem_desc *d, double *lambda_out,
     if (!(pr.w_shape > 0.0) || !(pr.w_rate > 0.0) || !std::isfinite(pr.w_shape)
         || !std::isfinite(pr.w_rate))
         return fail(XRDVI_EINVAL, "prior.w_shape and prior.w_rate must be > 0");
+    if (d->asymmetric != 0 && d->asymmetric != 1)
+        return fail(XRDVI_EINVAL, "asymmetric must be 0 or 1");
+    if (d->asymmetric && (!std::isfinite(pr.alpha_mean) || !(pr.alpha_sd > 0.0)
+                          || !std::isfinite(pr.alpha_sd)))
+        return fail(XRDVI_EINVAL,
+                    "prior.alpha_mean must be finite and prior.alpha_sd > 0");
     double lam = pr.lambda_h;
     double m = -INFINITY;
     for (int i = 0; i < d->N; ++i) m = std::max(m, d->y[i] - d->bg[i]);
@@ -423,7 +442,7 @@ int xrdvi_tape_create(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     if (S < 1 || S > kMaxSamples) return fail(XRDVI_EINVAL, "S must be in [1, 1024]");
     DeviceGuard g(ctx->device);
     const ProbDev &P = prob->P;
-    const size_t bytes = step_bytes(P.ntiles, P.K, P.T, S, P.N, P.cutoff == 0.0);
+    const size_t bytes = step_bytes(step_shape(P, S));
     void *mem = nullptr;
     hipError_t e = hipMalloc(&mem, bytes);
     if (e != hipSuccess)
@@ -432,7 +451,7 @@ int xrdvi_tape_create(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     t->prob = prob;
     t->device = ctx->device;
     t->mem = mem;
-    t->st = carve_step(mem, P.ntiles, P.K, P.T, S, P.N, P.cutoff == 0.0);
+    t->st = carve_step(mem, step_shape(P, S));
     *out = t;
     return XRDVI_OK;
     API_GUARD_END
@@ -458,10 +477,10 @@ int xrdvi_profile(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     DeviceGuard g(ctx->device);
     const ProbDev &P = prob->P;
     int rc = XRDVI_OK;
-    if (!ensure_ws(ctx, step_bytes(P.ntiles, P.K, P.T, S, P.N, P.cutoff == 0.0), &rc)) return rc;
-    StepDev st = carve_step(ctx->ws, P.ntiles, P.K, P.T, S, P.N, P.cutoff == 0.0);
+    if (!ensure_ws(ctx, step_bytes(step_shape(P, S)), &rc)) return rc;
+    StepDev st = carve_step(ctx->ws, step_shape(P, S));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    HIP_TRY(launch_phi_consts(P, S, phi, st.pk, s), "phi constants");
+    HIP_TRY(launch_phi_consts(P, S, phi, st.pk, st.pkr, s), "phi constants");
     if (P.cutoff > 0.0)
         HIP_TRY(launch_windows(P, S, phi, st.lo, st.hi, nullptr, s), "window plan");
     HIP_TRY(launch_plan(P, st, phi, s), "tile plan");
@@ -537,7 +556,8 @@ int xrdvi_tape_samples(xrdvi_ctx *ctx, const xrdvi_tape *tape,
     API_GUARD_BEGIN
     if (!ctx || !tape || !phi_out) return fail(XRDVI_EINVAL, "NULL argument");
     DeviceGuard g(ctx->device);
-    const size_t bytes = sizeof(double) * 4 * (size_t)tape->prob->P.K * tape->st.S;
+    const ProbDev &P = tape->prob->P;
+    const size_t bytes = sizeof(double) * P.D * (size_t)P.K * tape->st.S;
     HIP_TRY(hipMemcpyAsync(phi_out, tape->st.phi, bytes, hipMemcpyDeviceToDevice,
                            static_cast<hipStream_t>(stream)),
             "copy samples");

@@ -16,6 +16,13 @@
 //   G = (cG / w) 2^(-q2^2),  L = (cL / w) / (1 + q2^2),
 //   cG = 2 sqrt(ln2 / pi), cL = 2 / pi
 // (unit-area Gaussian and Lorentzian of full width at half maximum w).
+//
+// Asymmetric peaks (Appendix A.2, asymmetry factor A(x; alpha): alpha on the
+// high-angle side of the peak, 1 below it): the full width is w below rho
+// and alpha w from rho up, and the peak is scaled by 2 / (1 + alpha) so that
+// it keeps unit area; the same formulas hold with q2 = 2 (x - rho) / (A w)
+// and the prefactors multiplied by 2 / (1 + alpha).  Each phase then has a
+// fifth latent, alpha = exp(z_alpha) with a normal prior.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -44,11 +51,14 @@ constexpr double kTwoPi = 6.28318530717958647693;
 // each phase).
 struct ProbDev {
     int N, K, T, ntiles;
+    int D;                            // latent types per phase: 4, or 5 with
+                                      // the asymmetry alpha
     double cutoff;
     double lambda, mu_sd, w_shape, w_rate;
+    double a_mean, a_sd;              // normal prior on alpha (D = 5)
     // log-density constants: ln lambda, -ln(mu_sd sqrt(2 pi)),
-    // shape ln(rate) - lgamma(shape)
-    double c_h, c_mu, c_w;
+    // shape ln(rate) - lgamma(shape), -ln(a_sd sqrt(2 pi))
+    double c_h, c_mu, c_w, c_a;
     const double *x, *y, *bg, *lgy;   // [N]; lgy = ln y!
     const float *u;                   // [ntiles * kTile] x_i - xref_tile
     const int *off;                   // [K + 1]
@@ -59,22 +69,31 @@ struct ProbDev {
 };
 
 // Per-step state of one analysis with S samples.
+// Number of adjoint sums per (sample, phase): six, or six per side of the
+// peak (below / above rho) for asymmetric peaks.
+__host__ __device__ inline int num_sums(int D) { return D == 5 ? 12 : 6; }
+
 struct StepDev {
     int S;
-    double *eps;      // [S][4K] noise used
-    double *phi;      // [S][4K] constrained samples (h, mu, w, r rows)
-    float4 *pk;       // [S][K] (2/w, h(1-r)cG/w, h r cL/w, mu) in FP32
+    double *eps;      // [S][D K] noise used
+    double *phi;      // [S][D K] constrained samples (h, mu, w, r[, alpha])
+    float4 *pk;       // [S][K] (2/w, h(1-r)cG n/w, h r cL n/w, mu) in FP32,
+                      // n = 2/(1+alpha) (1 for symmetric peaks)
+    float *pkr;       // [S][K] 2/(alpha w): the high-angle side (D = 5)
     double *lpj;      // [S][K] log prior + log|J|
     double *lpb;      // [S][ceil(K/64)] per-wave sums of lpj
     int *lo, *hi;     // [S][T] window plan (sorted peak order)
     int4 *rng;        // [S][ntiles][K] peak ranges (ja, ga, gb, jb) of a
                       // tile: [ja, jb) reach the tile, [ga, gb) need G
+    int2 *rng2;       // [S][ntiles][K] (jr, jl) for D = 5: peaks before jr
+                      // lie at or below every point of the tile, peaks from
+                      // jl above every point
     float *rres;      // [S][N] residual y/f - 1 (windowed mode)
-    double *pw;       // [K][S][6] adjoint sums per (phase, sample)
+    double *pw;       // [K][S][num_sums] adjoint sums per (phase, sample)
                       // (windowed mode)
     double *llp;      // [S][ntiles] per-tile log-likelihood
-    float *part;      // [ntiles][K][S][6] adjoint tile sums
-    double *sd;       // [4K] exp(logscale)
+    float *part;      // [ntiles][K][S][num_sums] adjoint tile sums
+    double *sd;       // [D K] exp(logscale)
 };
 
 // Read-only view of data that no kernel of the current launch writes:
@@ -141,11 +160,19 @@ __device__ __forceinline__ double softplus(double a) {
 }
 
 // FP32 kernel constants of one (sample, phase).
+// nrm = 2 / (1 + alpha) for asymmetric peaks, 1 otherwise.
 __device__ __forceinline__ float4 phase_consts(double h, double mu, double w,
-                                               double r) {
+                                               double r, double nrm = 1.0) {
     const double iw = 1.0 / w;
-    return make_float4((float)(2.0 * iw), (float)(h * (1.0 - r) * kCG * iw),
-                       (float)(h * r * kCL * iw), (float)mu);
+    return make_float4((float)(2.0 * iw),
+                       (float)(h * (1.0 - r) * kCG * iw * nrm),
+                       (float)(h * r * kCL * iw * nrm), (float)mu);
+}
+__device__ __forceinline__ double asym_norm(double alpha) {
+    return 2.0 / (1.0 + alpha);
+}
+__device__ __forceinline__ float asym_iw2(double w, double alpha) {
+    return (float)(2.0 / (alpha * w));
 }
 
 // ---- window plan ---------------------------------------------------------
@@ -169,16 +196,17 @@ __device__ inline int upper_bound_x(const double *x, int n, double v) {
     return lo;
 }
 
-// Grid range [lo, hi) with rho - c w <= x_i <= rho + c w; each bound is one
+// Grid range [lo, hi) with rho - c w <= x_i <= rho + c w (rho + (c w) alpha
+// for asymmetric peaks, alpha > 0; pass 1 otherwise); each bound is one
 // rounded FP64 operation (no contraction), as in the model's definition.
 __device__ inline int2 window_of(const ProbDev &P, double p, double mu,
-                                 double w) {
+                                 double w, double alpha) {
 #pragma clang fp contract(off)
     if (P.cutoff == 0.0) return make_int2(0, P.N);
     const double rho = p + mu;
     const double hw = P.cutoff * w;
     const double a = rho - hw;
-    const double b = rho + hw;
+    const double b = rho + (P.D == 5 ? hw * alpha : hw);
     const int lo = lower_bound_x(P.x, P.N, a);
     int hi = upper_bound_x(P.x, P.N, b);
     if (hi < lo) hi = lo;
@@ -225,9 +253,23 @@ __device__ inline int first_greater_d(const double *v, int a, int b,
     return a;
 }
 
-// Range entry of (sample s, tile t, phase k); phi: [S][4][K].
+// First j in [a, b) with p[j] + mu > key (FP64 sum, as the peak centre
+// rho is formed everywhere else); monotone because p is sorted.
+__device__ inline int first_centre_above(const double *p, int a, int b,
+                                         double mu, double key) {
+#pragma clang fp contract(off)
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (p[mid] + mu > key) b = mid; else a = mid + 1;
+    }
+    return a;
+}
+
+// Range entry of (sample s, tile t, phase k); phi: [S][D][K].  For
+// asymmetric peaks *side receives (jr, jl) with ga <= jr <= jl <= gb.
 __device__ inline int4 tile_range(const ProbDev &P, const StepDev &st,
-                                  const double *phi, int s, int t, int k) {
+                                  const double *phi, int s, int t, int k,
+                                  int2 *side) {
     const int a = P.off[k], b = P.off[k + 1];
     const int i0 = t * kTile, i1 = min(i0 + kTile, P.N);
     int ja = a, jb = b;
@@ -237,12 +279,19 @@ __device__ inline int4 tile_range(const ProbDev &P, const StepDev &st,
         ja = first_greater(hi, a, b, i0);
         jb = first_not_less(lo, ja, b, i1);
     }
-    const double *ph = phi + (size_t)s * 4 * P.K;
+    const double *ph = phi + (size_t)s * P.D * P.K;
     const double mu = ph[P.K + k], w = ph[2 * P.K + k];
-    const double reach = kGaussReach * w;
-    // Gaussian relevant: p + mu + reach >= x[i0] and p + mu - reach <= x[i1-1]
-    const int ga = first_not_less_d(P.pos, ja, jb, P.x[i0] - mu - reach);
+    const double alpha = P.D == 5 ? ph[4 * P.K + k] : 1.0;
+    const double reach = kGaussReach * w;       // below rho
+    const double reach_hi = reach * alpha;      // above rho
+    // Gaussian relevant: p + mu + reach_hi >= x[i0], p + mu - reach <= x[i1-1]
+    const int ga = first_not_less_d(P.pos, ja, jb, P.x[i0] - mu - reach_hi);
     const int gb = first_greater_d(P.pos, ga, jb, P.x[i1 - 1] - mu + reach);
+    if (side) {
+        const int jr = first_centre_above(P.pos, ga, gb, mu, P.x[i0]);
+        const int jl = first_centre_above(P.pos, jr, gb, mu, P.x[i1 - 1]);
+        *side = make_int2(jr, jl);
+    }
     return make_int4(ja, ga, gb, jb);
 }
 
@@ -284,9 +333,12 @@ struct FusedSmem {
 //
 // Four waves split the phases (k = wave, wave + 4, ...).  Every wave holds
 // the same kTile points, kPPL per lane (point i0 + p*64 + lane).  Peak data
-// are wave-uniform (scalar loads).  Per phase the peaks run in three
-// segments: [ja, ga) and [gb, jb) need only the Lorentzian, [ga, gb) both
-// components.  WIN: each lane is masked by the peak's exact window.
+// are wave-uniform (scalar loads).  Per phase the peaks run in segments:
+// [ja, ga) and [gb, jb) need only the Lorentzian, [ga, gb) both components.
+// For asymmetric peaks [ga, gb) splits further at jr and jl: the tile lies
+// above the centres of [ja, jr), straddles those of [jr, jl) and lies below
+// those of [jl, jb), so only [jr, jl) picks the width per point.
+// WIN: each lane is masked by the peak's exact window.
 template <bool WIN>
 struct PeakMask {
     int lo, hi;
@@ -297,7 +349,149 @@ struct PeakMask {
     }
 };
 
-template <bool WIN, bool GRAD>
+// Per-peak data of one phase seen by a segment loop.
+struct SegPeaks {
+    cptr<float> pt;       // tile-relative positions
+    cptr<float> inten;
+    cptr<int> wlo, whi;   // windows (WIN)
+};
+
+// Side of a segment: the points lie below the peak centres (or the peaks are
+// symmetric), above them, or on both sides (chosen per point).
+enum { kBelow = 0, kAbove = 1, kBoth = 2 };
+
+// q2 = 2 (x - rho) / (A w) of point p for peak position ptj.
+template <int SIDE>
+__device__ __forceinline__ float seg_q2(float ptj, float iw2, float iw2r,
+                                        float uq, float uqr) {
+    if (SIDE == kBelow) return fmaf(-ptj, iw2, uq);
+    if (SIDE == kAbove) return fmaf(-ptj, iw2r, uqr);
+    const float ql = fmaf(-ptj, iw2, uq);
+    const float qr = fmaf(-ptj, iw2r, uqr);
+    return ql >= 0.f ? qr : ql;
+}
+
+template <bool WIN, bool GAUSS, int SIDE>
+__device__ __forceinline__ void fwd_segment(const SegPeaks &pk, int j0, int j1,
+                                            const int (&idx)[kPPL],
+                                            const float (&uq)[kPPL],
+                                            const float (&uqr)[kPPL],
+                                            float iw2, float iw2r,
+                                            float (&accL)[kPPL],
+                                            float (&accG)[kPPL]) {
+#pragma unroll 2
+    for (int j = j0; j < j1; ++j) {
+        const float ptj = pk.pt[j];
+        const float I = pk.inten[j];
+        PeakMask<WIN> mk;
+        if (WIN) { mk.lo = pk.wlo[j]; mk.hi = pk.whi[j]; }
+#pragma unroll
+        for (int p = 0; p < kPPL; ++p) {
+            const float q2 = seg_q2<SIDE>(ptj, iw2, iw2r, uq[p], uqr[p]);
+            const float tt = mk.apply(idx[p], fmaf(q2, q2, 1.0f));
+            accL[p] = fmaf(I, rcp_f32(tt), accL[p]);
+            if (GAUSS) accG[p] = fmaf(I, exp2_f32(1.0f - tt), accG[p]);
+        }
+    }
+}
+
+// Per point and phase: l0 = sum I l, l1 = sum I l^2 q2, l2 = sum I l^2,
+// e0 = sum I e, e1 = sum I e q2, e2 = sum I e q2^2 (e = 2^(-q2^2),
+// l = 1/(1 + q2^2)).
+struct Acc6 {
+    float l0[kPPL], l1[kPPL], l2[kPPL], e0[kPPL], e1[kPPL], e2[kPPL];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int p = 0; p < kPPL; ++p)
+            l0[p] = l1[p] = l2[p] = e0[p] = e1[p] = e2[p] = 0.f;
+    }
+};
+
+// Adds the peak terms of [j0, j1) to `lo` (points below the centres, or
+// symmetric peaks) or `hi` (points above).
+template <bool WIN, bool GAUSS, int SIDE>
+__device__ __forceinline__ void adj_segment(const SegPeaks &pk, int j0, int j1,
+                                            const int (&idx)[kPPL],
+                                            const float (&uq)[kPPL],
+                                            const float (&uqr)[kPPL],
+                                            float iw2, float iw2r, Acc6 &lo,
+                                            Acc6 &hi) {
+#pragma unroll 2
+    for (int j = j0; j < j1; ++j) {
+        const float ptj = pk.pt[j];
+        const float I = pk.inten[j];
+        PeakMask<WIN> mk;
+        if (WIN) { mk.lo = pk.wlo[j]; mk.hi = pk.whi[j]; }
+#pragma unroll
+        for (int p = 0; p < kPPL; ++p) {
+            const float q2 = seg_q2<SIDE>(ptj, iw2, iw2r, uq[p], uqr[p]);
+            const float tt = mk.apply(idx[p], fmaf(q2, q2, 1.0f));
+            const float l = rcp_f32(tt);
+            const float Il = I * l;
+            const float Ill = Il * l;
+            float Ie = 0.f, Ieq = 0.f;
+            if (GAUSS) {
+                Ie = I * exp2_f32(1.0f - tt);
+                Ieq = Ie * q2;
+            }
+            if (SIDE != kBoth) {
+                Acc6 &a = SIDE == kAbove ? hi : lo;
+                a.l0[p] += Il;
+                a.l2[p] += Ill;
+                a.l1[p] = fmaf(Ill, q2, a.l1[p]);
+                if (GAUSS) {
+                    a.e0[p] += Ie;
+                    a.e1[p] += Ieq;
+                    a.e2[p] = fmaf(Ieq, q2, a.e2[p]);
+                }
+            } else {
+                const float Illq = Ill * q2, Ieqq = Ieq * q2;
+                const float fu = fmaf(-ptj, iw2, uq[p]) >= 0.f ? 1.f : 0.f;
+                const float fd = 1.f - fu;
+                hi.l0[p] = fmaf(fu, Il, hi.l0[p]);
+                lo.l0[p] = fmaf(fd, Il, lo.l0[p]);
+                hi.l2[p] = fmaf(fu, Ill, hi.l2[p]);
+                lo.l2[p] = fmaf(fd, Ill, lo.l2[p]);
+                hi.l1[p] = fmaf(fu, Illq, hi.l1[p]);
+                lo.l1[p] = fmaf(fd, Illq, lo.l1[p]);
+                if (GAUSS) {
+                    hi.e0[p] = fmaf(fu, Ie, hi.e0[p]);
+                    lo.e0[p] = fmaf(fd, Ie, lo.e0[p]);
+                    hi.e1[p] = fmaf(fu, Ieq, hi.e1[p]);
+                    lo.e1[p] = fmaf(fd, Ieq, lo.e1[p]);
+                    hi.e2[p] = fmaf(fu, Ieqq, hi.e2[p]);
+                    lo.e2[p] = fmaf(fd, Ieqq, lo.e2[p]);
+                }
+            }
+        }
+    }
+}
+
+// The six residual-weighted sums of `a` over the tile, wave totals written by
+// lane 0 to dst[0..5] in the order (e0, e1, e2, l0, l1, l2).
+__device__ __forceinline__ void store_sums(const Acc6 &a,
+                                           const float (&rres)[kPPL],
+                                           int lane, float *dst) {
+    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f;
+#pragma unroll
+    for (int p = 0; p < kPPL; ++p) {
+        v0 = fmaf(rres[p], a.e0[p], v0);
+        v1 = fmaf(rres[p], a.e1[p], v1);
+        v2 = fmaf(rres[p], a.e2[p], v2);
+        v3 = fmaf(rres[p], a.l0[p], v3);
+        v4 = fmaf(rres[p], a.l1[p], v4);
+        v5 = fmaf(rres[p], a.l2[p], v5);
+    }
+    v0 = wave_total_f32(v0); v1 = wave_total_f32(v1);
+    v2 = wave_total_f32(v2); v3 = wave_total_f32(v3);
+    v4 = wave_total_f32(v4); v5 = wave_total_f32(v5);
+    if (lane == 0) {
+        dst[0] = v0; dst[1] = v1; dst[2] = v2;
+        dst[3] = v3; dst[4] = v4; dst[5] = v5;
+    }
+}
+
+template <bool WIN, bool GRAD, bool ASYM>
 __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
                            float *f_out, FusedSmem &sm) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -308,10 +502,18 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
     cptr<float> pk = as_const(reinterpret_cast<const float *>(st.pk + (size_t)s * P.K));
     cptr<int> rg = as_const(reinterpret_cast<const int *>(
         st.rng + ((size_t)s * P.ntiles + t) * P.K));
-    cptr<float> ptt = as_const(P.pt + (size_t)t * P.T);
-    cptr<float> inten = as_const(P.inten);
-    cptr<int> wlo = as_const(st.lo + (size_t)s * P.T);
-    cptr<int> whi = as_const(st.hi + (size_t)s * P.T);
+    cptr<float> pkr = nullptr;
+    cptr<int> rg2 = nullptr;
+    if (ASYM) {
+        pkr = as_const(st.pkr + (size_t)s * P.K);
+        rg2 = as_const(reinterpret_cast<const int *>(
+            st.rng2 + ((size_t)s * P.ntiles + t) * P.K));
+    }
+    SegPeaks sp;
+    sp.pt = as_const(P.pt + (size_t)t * P.T);
+    sp.inten = as_const(P.inten);
+    sp.wlo = as_const(st.lo + (size_t)s * P.T);
+    sp.whi = as_const(st.hi + (size_t)s * P.T);
 
     float u[kPPL];
     int idx[kPPL];
@@ -332,32 +534,26 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
         if (ja >= jb) continue;
         const float iw2 = in_vgpr(pk[4 * k]);
         const float aG = pk[4 * k + 1], aL = pk[4 * k + 2], mu = pk[4 * k + 3];
-        float uq[kPPL], accL[kPPL], accG[kPPL];
+        const float iw2r = ASYM ? in_vgpr(pkr[k]) : iw2;
+        float uq[kPPL], uqr[kPPL], accL[kPPL], accG[kPPL];
 #pragma unroll
         for (int p = 0; p < kPPL; ++p) {
             uq[p] = (u[p] - mu) * iw2;
+            uqr[p] = ASYM ? (u[p] - mu) * iw2r : uq[p];
             accL[p] = 0.f;
             accG[p] = 0.f;
         }
-        // Lorentzian-only and full segments
-        for (int seg = 0; seg < 3; ++seg) {
-            const int j0 = seg == 0 ? ja : (seg == 1 ? ga : gb);
-            const int j1 = seg == 0 ? ga : (seg == 1 ? gb : jb);
-            const bool gauss = seg == 1;
-#pragma unroll 2
-            for (int j = j0; j < j1; ++j) {
-                const float ptj = ptt[j];
-                const float I = inten[j];
-                PeakMask<WIN> mk;
-                if (WIN) { mk.lo = wlo[j]; mk.hi = whi[j]; }
-#pragma unroll
-                for (int p = 0; p < kPPL; ++p) {
-                    const float q2 = fmaf(-ptj, iw2, uq[p]);
-                    const float tt = mk.apply(idx[p], fmaf(q2, q2, 1.0f));
-                    accL[p] = fmaf(I, rcp_f32(tt), accL[p]);
-                    if (gauss) accG[p] = fmaf(I, exp2_f32(1.0f - tt), accG[p]);
-                }
-            }
+        if (ASYM) {
+            const int jr = rg2[2 * k], jl = rg2[2 * k + 1];
+            fwd_segment<WIN, false, kAbove>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, true, kAbove>(sp, ga, jr, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, true, kBoth>(sp, jr, jl, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, true, kBelow>(sp, jl, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, false, kBelow>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
+        } else {
+            fwd_segment<WIN, false, kBelow>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, true, kBelow>(sp, ga, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, false, kBelow>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
         }
 #pragma unroll
         for (int p = 0; p < kPPL; ++p)
@@ -397,79 +593,47 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
     }
     if (!GRAD) return;
 
-    // ---------------- adjoint: recompute every peak value
-    // per point and phase: yl = sum I l, yl1 = sum I l^2 q2, yl2 = sum I l^2,
-    // ye = sum I e, ye1 = sum I e q2, ye2 = sum I e q2^2; the phase's six
-    // sums are then sum_points (y/f - 1) * (...), reduced over the wave.
+    // ---------------- adjoint: recompute every peak value; the phase's sums
+    // are sum_points (y/f - 1) * (per-point sums), reduced over the wave
+    constexpr int NS = ASYM ? 12 : 6;
     float rres[kPPL];
 #pragma unroll
     for (int p = 0; p < kPPL; ++p) rres[p] = sm.rres[p * kWave + lane];
 
     for (int k = wv; k < P.K; k += kWaves) {
-        float *dst = st.part + (((size_t)t * P.K + k) * st.S + s) * 6;
+        float *dst = st.part + (((size_t)t * P.K + k) * st.S + s) * NS;
         const int ja = rg[4 * k], ga = rg[4 * k + 1], gb = rg[4 * k + 2],
                   jb = rg[4 * k + 3];
         if (ja >= jb) {
-            if (lane < 6) dst[lane] = 0.f;
+            if (lane < NS) dst[lane] = 0.f;
             continue;
         }
         const float iw2 = in_vgpr(pk[4 * k]);
         const float mu = pk[4 * k + 3];
-        float uq[kPPL], yl0[kPPL], yl1[kPPL], yl2[kPPL], ye0[kPPL], ye1[kPPL],
-            ye2[kPPL];
+        const float iw2r = ASYM ? in_vgpr(pkr[k]) : iw2;
+        float uq[kPPL], uqr[kPPL];
 #pragma unroll
         for (int p = 0; p < kPPL; ++p) {
             uq[p] = (u[p] - mu) * iw2;
-            yl0[p] = yl1[p] = yl2[p] = 0.f;
-            ye0[p] = ye1[p] = ye2[p] = 0.f;
+            uqr[p] = ASYM ? (u[p] - mu) * iw2r : uq[p];
         }
-        for (int seg = 0; seg < 3; ++seg) {
-            const int j0 = seg == 0 ? ja : (seg == 1 ? ga : gb);
-            const int j1 = seg == 0 ? ga : (seg == 1 ? gb : jb);
-            const bool gauss = seg == 1;
-#pragma unroll 2
-            for (int j = j0; j < j1; ++j) {
-                const float ptj = ptt[j];
-                const float I = inten[j];
-                PeakMask<WIN> mk;
-                if (WIN) { mk.lo = wlo[j]; mk.hi = whi[j]; }
-#pragma unroll
-                for (int p = 0; p < kPPL; ++p) {
-                    const float q2 = fmaf(-ptj, iw2, uq[p]);
-                    const float tt = mk.apply(idx[p], fmaf(q2, q2, 1.0f));
-                    const float l = rcp_f32(tt);
-                    const float Il = I * l;
-                    const float Ill = Il * l;
-                    yl0[p] += Il;
-                    yl2[p] += Ill;
-                    yl1[p] = fmaf(Ill, q2, yl1[p]);
-                    if (gauss) {
-                        const float Ie = I * exp2_f32(1.0f - tt);
-                        const float Ieq = Ie * q2;
-                        ye0[p] += Ie;
-                        ye1[p] += Ieq;
-                        ye2[p] = fmaf(Ieq, q2, ye2[p]);
-                    }
-                }
-            }
+        Acc6 lo, hi;
+        lo.zero();
+        if (ASYM) {
+            hi.zero();
+            const int jr = rg2[2 * k], jl = rg2[2 * k + 1];
+            adj_segment<WIN, false, kAbove>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, lo, hi);
+            adj_segment<WIN, true, kAbove>(sp, ga, jr, idx, uq, uqr, iw2, iw2r, lo, hi);
+            adj_segment<WIN, true, kBoth>(sp, jr, jl, idx, uq, uqr, iw2, iw2r, lo, hi);
+            adj_segment<WIN, true, kBelow>(sp, jl, gb, idx, uq, uqr, iw2, iw2r, lo, hi);
+            adj_segment<WIN, false, kBelow>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, lo, hi);
+        } else {
+            adj_segment<WIN, false, kBelow>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, lo, hi);
+            adj_segment<WIN, true, kBelow>(sp, ga, gb, idx, uq, uqr, iw2, iw2r, lo, hi);
+            adj_segment<WIN, false, kBelow>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, lo, hi);
         }
-        float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f;
-#pragma unroll
-        for (int p = 0; p < kPPL; ++p) {
-            v0 = fmaf(rres[p], ye0[p], v0);
-            v1 = fmaf(rres[p], ye1[p], v1);
-            v2 = fmaf(rres[p], ye2[p], v2);
-            v3 = fmaf(rres[p], yl0[p], v3);
-            v4 = fmaf(rres[p], yl1[p], v4);
-            v5 = fmaf(rres[p], yl2[p], v5);
-        }
-        v0 = wave_total_f32(v0); v1 = wave_total_f32(v1);
-        v2 = wave_total_f32(v2); v3 = wave_total_f32(v3);
-        v4 = wave_total_f32(v4); v5 = wave_total_f32(v5);
-        if (lane == 0) {
-            dst[0] = v0; dst[1] = v1; dst[2] = v2;
-            dst[3] = v3; dst[4] = v4; dst[5] = v5;
-        }
+        store_sums(lo, rres, lane, dst);
+        if (ASYM) store_sums(hi, rres, lane, dst + 6);
     }
 }
 
@@ -478,23 +642,29 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
 // One block of kWaves waves per (sample s, phase k); wave w takes peaks
 // a + w, a + w + kWaves, ...  For every peak the lanes cover consecutive
 // points of its window (64 at a time); x - rho is formed in FP64 and
-// rounded to FP32.  Six sums accumulate per lane over the wave's peaks, are
-// reduced over the wave, then over the waves in fixed order.
+// rounded to FP32 (its sign picks the side of an asymmetric peak).  Six
+// sums (twelve: six per side) accumulate per lane over the wave's peaks,
+// are reduced over the wave, then over the waves in fixed order.
+template <bool ASYM>
 __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
-                                     int s, int k, double (*red)[6]) {
+                                     int s, int k, double (*red)[12]) {
+    constexpr int NS = ASYM ? 12 : 6;
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int K = P.K;
-    const double *ph = st.phi + (size_t)s * 4 * K;
+    const double *ph = st.phi + (size_t)s * P.D * K;
     const double mu = ph[K + k];
     const float iw2 = (float)(2.0 / ph[2 * K + k]);
+    const float iw2r = ASYM ? asym_iw2(ph[2 * K + k], ph[4 * K + k]) : iw2;
     const float *__restrict__ rres = st.rres + (size_t)s * P.N;
     cptr<int> wlo = as_const(st.lo + (size_t)s * P.T);
     cptr<int> whi = as_const(st.hi + (size_t)s * P.T);
     cptr<double> pos = as_const(P.pos);
     cptr<float> inten = as_const(P.inten);
     const int a = P.off[k], b = P.off[k + 1];
-    float e0 = 0.f, e1 = 0.f, e2 = 0.f, l0 = 0.f, l1 = 0.f, l2 = 0.f;
+    float acc[NS];
+#pragma unroll
+    for (int c = 0; c < NS; ++c) acc[c] = 0.f;
     for (int j = a + wv; j < b; j += kWaves) {
         const int lo = wlo[j], hi = whi[j];
         const float I = inten[j];
@@ -504,34 +674,59 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
             const bool valid = i < hi;
             const int ii = valid ? i : lo;
             const float R = valid ? rres[ii] * I : 0.f;
-            const float q2 = (float)(P.x[ii] - rho) * iw2;
+            const double d = P.x[ii] - rho;
+            const bool up = ASYM && d >= 0.0;
+            const float q2 = (float)d * (up ? iw2r : iw2);
             const float tt = fmaf(q2, q2, 1.0f);
             const float l = rcp_f32(tt);
             const float Rl = R * l;
             const float Rll = Rl * l;
-            l0 += Rl;
-            l2 += Rll;
-            l1 = fmaf(Rll, q2, l1);
-            if (__builtin_expect(__any(valid && tt < 81.0f), 0)) {
-                const float Re = R * exp2_f32(1.0f - tt);
-                const float Req = Re * q2;
-                e0 += Re;
-                e1 += Req;
-                e2 = fmaf(Req, q2, e2);
+            float Re = 0.f, Req = 0.f;
+            const bool gauss = __builtin_expect(__any(valid && tt < 81.0f), 0);
+            if (gauss) {
+                Re = R * exp2_f32(1.0f - tt);
+                Req = Re * q2;
+            }
+            if (!ASYM) {
+                acc[3] += Rl;
+                acc[5] += Rll;
+                acc[4] = fmaf(Rll, q2, acc[4]);
+                if (gauss) {
+                    acc[0] += Re;
+                    acc[1] += Req;
+                    acc[2] = fmaf(Req, q2, acc[2]);
+                }
+            } else {
+                const float Rllq = Rll * q2, Reqq = Req * q2;
+                const float fu = up ? 1.f : 0.f, fd = 1.f - fu;
+                acc[3] = fmaf(fd, Rl, acc[3]);
+                acc[9] = fmaf(fu, Rl, acc[9]);
+                acc[5] = fmaf(fd, Rll, acc[5]);
+                acc[11] = fmaf(fu, Rll, acc[11]);
+                acc[4] = fmaf(fd, Rllq, acc[4]);
+                acc[10] = fmaf(fu, Rllq, acc[10]);
+                if (gauss) {
+                    acc[0] = fmaf(fd, Re, acc[0]);
+                    acc[6] = fmaf(fu, Re, acc[6]);
+                    acc[1] = fmaf(fd, Req, acc[1]);
+                    acc[7] = fmaf(fu, Req, acc[7]);
+                    acc[2] = fmaf(fd, Reqq, acc[2]);
+                    acc[8] = fmaf(fu, Reqq, acc[8]);
+                }
             }
         }
     }
-    e0 = wave_total_f32(e0); e1 = wave_total_f32(e1); e2 = wave_total_f32(e2);
-    l0 = wave_total_f32(l0); l1 = wave_total_f32(l1); l2 = wave_total_f32(l2);
+#pragma unroll
+    for (int c = 0; c < NS; ++c) acc[c] = wave_total_f32(acc[c]);
     if (lane == 0) {
-        red[wv][0] = e0; red[wv][1] = e1; red[wv][2] = e2;
-        red[wv][3] = l0; red[wv][4] = l1; red[wv][5] = l2;
+#pragma unroll
+        for (int c = 0; c < NS; ++c) red[wv][c] = acc[c];
     }
     __syncthreads();
-    if (threadIdx.x < 6) {
+    if (threadIdx.x < NS) {
         double v = 0.0;
         for (int w = 0; w < kWaves; ++w) v += red[w][threadIdx.x];
-        st.pw[((size_t)k * st.S + s) * 6 + threadIdx.x] = v;
+        st.pw[((size_t)k * st.S + s) * NS + threadIdx.x] = v;
     }
 }
 

@@ -19,7 +19,7 @@ hipError_t launch_sample(const ProbDev &P, const StepDev &st,
                          const double *eps, uint64_t seed, uint64_t step,
                          hipStream_t stream);
 hipError_t launch_phi_consts(const ProbDev &P, int S, const double *phi,
-                             float4 *pk, hipStream_t stream);
+                             float4 *pk, float *pkr, hipStream_t stream);
 hipError_t launch_windows(const ProbDev &P, int S, const double *phi, int *lo,
                           int *hi, const int *perm, hipStream_t stream);
 hipError_t launch_plan(const ProbDev &P, const StepDev &st, const double *phi,
@@ -41,14 +41,26 @@ void set_error(const std::string &msg);
 
 constexpr int kMaxSamples = 1024;
 
-// Bytes of per-step device state for (N, K, T, S), laid out by carve_step;
-// the tile partial sums exist only for the dense (cutoff 0) path.
-size_t step_bytes(int ntiles, int K, int T, int S, int N, bool dense);
+// Sizes that fix the per-step device state of one analysis.
+struct StepShape {
+    int ntiles, K, T, S, N;
+    int D;          // latent types per phase (4, or 5 with asymmetry)
+    bool dense;     // cutoff 0: the adjoint keeps per-tile partial sums
+};
+inline StepShape step_shape(const ProbDev &P, int S) {
+    return StepShape{P.ntiles, P.K, P.T, S, P.N, P.D, P.cutoff == 0.0};
+}
+// Bytes of per-step device state, laid out by carve_step.
+size_t step_bytes(const StepShape &sh);
 // Carves StepDev buffers out of `base` (256-byte aligned pieces).
-StepDev carve_step(void *base, int ntiles, int K, int T, int S, int N,
-                   bool dense);
+StepDev carve_step(void *base, const StepShape &sh);
 
 inline int num_tiles(int N) { return (N + kTile - 1) / kTile; }
+
+// Latent types per phase of a description.
+inline int latent_types(const xrdvi_problem_desc &d) {
+    return d.asymmetric ? 5 : 4;
+}
 
 // Device bytes of a prepared problem and its upload (validated desc,
 // resolved lambda) into `base`; fills P and the sorted-to-caller peak

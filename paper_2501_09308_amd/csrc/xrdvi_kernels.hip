@@ -40,13 +40,21 @@ __global__ __launch_bounds__(256) void k_sample(
 
 // Constants of given constrained samples (profile entry).
 __global__ void k_phi_consts(ProbDev P, int S, const double *__restrict__ phi,
-                             float4 *pk) {
+                             float4 *pk, float *pkr) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
     if (k >= P.K || s >= S) return;
-    const double *ph = phi + (size_t)s * 4 * P.K;
-    pk[(size_t)s * P.K + k] =
-        phase_consts(ph[k], ph[P.K + k], ph[2 * P.K + k], ph[3 * P.K + k]);
+    const double *ph = phi + (size_t)s * P.D * P.K;
+    const size_t o = (size_t)s * P.K + k;
+    if (P.D == 5) {
+        const double al = ph[4 * P.K + k];
+        pk[o] = phase_consts(ph[k], ph[P.K + k], ph[2 * P.K + k],
+                             ph[3 * P.K + k], asym_norm(al));
+        pkr[o] = asym_iw2(ph[2 * P.K + k], al);
+    } else {
+        pk[o] = phase_consts(ph[k], ph[P.K + k], ph[2 * P.K + k],
+                             ph[3 * P.K + k]);
+    }
 }
 
 // a2: one thread per (sample, peak).  perm != NULL writes the caller's
@@ -68,18 +76,19 @@ __global__ void k_plan(ProbDev P, StepDev st, const double *__restrict__ phi) {
 }
 
 // a3 + a4 (+ a6): grid (ntiles, S), kBlock threads.
-template <bool WIN, bool GRAD>
+template <bool WIN, bool GRAD, bool ASYM>
 __global__ __launch_bounds__(kBlock) void k_fused(ProbDev P, StepDev st,
                                                   float *f_out) {
     __shared__ FusedSmem sm;
-    fused_tile<WIN, GRAD>(P, st, blockIdx.x, blockIdx.y, f_out, sm);
+    fused_tile<WIN, GRAD, ASYM>(P, st, blockIdx.x, blockIdx.y, f_out, sm);
 }
 
 // a6 (windowed): peak-major adjoint, one block per (sample, phase);
 // grid (K, S), kBlock threads.
+template <bool ASYM>
 __global__ __launch_bounds__(kBlock) void k_adjoint_win(ProbDev P, StepDev st) {
-    __shared__ double red[kWaves][6];
-    adjoint_phase(P, st, blockIdx.y, blockIdx.x, red);
+    __shared__ double red[kWaves][12];
+    adjoint_phase<ASYM>(P, st, blockIdx.y, blockIdx.x, red);
 }
 
 // a5: one block of 1024 threads.
@@ -134,9 +143,9 @@ hipError_t launch_sample(const ProbDev &P, const StepDev &st,
 }
 
 hipError_t launch_phi_consts(const ProbDev &P, int S, const double *phi,
-                             float4 *pk, hipStream_t stream) {
+                             float4 *pk, float *pkr, hipStream_t stream) {
     dim3 g((P.K + kWave - 1) / kWave, S);
-    k_phi_consts<<<g, kWave, 0, stream>>>(P, S, phi, pk);
+    k_phi_consts<<<g, kWave, 0, stream>>>(P, S, phi, pk, pkr);
     return hipGetLastError();
 }
 
@@ -161,23 +170,30 @@ hipError_t launch_plan(const ProbDev &P, const StepDev &st, const double *phi,
 
 // Dense: one fused forward + adjoint launch.  Windowed: the forward writes
 // the residual, the peak-major adjoint follows when `grad` is set.
-hipError_t launch_fused(const ProbDev &P, const StepDev &st, bool grad,
-                        float *f_out, hipStream_t stream) {
+template <bool ASYM>
+static void launch_fused_t(const ProbDev &P, const StepDev &st, bool grad,
+                           float *f_out, hipStream_t stream) {
     dim3 g(P.ntiles, st.S);
     if (P.cutoff > 0.0) {
         StepDev sf = st;
         if (!grad) sf.rres = nullptr;
-        k_fused<true, false><<<g, kBlock, 0, stream>>>(P, sf, f_out);
+        k_fused<true, false, ASYM><<<g, kBlock, 0, stream>>>(P, sf, f_out);
         if (grad) {
             dim3 ga(P.K, st.S);
-            k_adjoint_win<<<ga, kBlock, 0, stream>>>(P, st);
+            k_adjoint_win<ASYM><<<ga, kBlock, 0, stream>>>(P, st);
         }
     } else {
         StepDev sd = st;
         sd.rres = nullptr;      // dense: the residual stays in LDS
-        if (grad) k_fused<false, true><<<g, kBlock, 0, stream>>>(P, sd, f_out);
-        else k_fused<false, false><<<g, kBlock, 0, stream>>>(P, sd, f_out);
+        if (grad) k_fused<false, true, ASYM><<<g, kBlock, 0, stream>>>(P, sd, f_out);
+        else k_fused<false, false, ASYM><<<g, kBlock, 0, stream>>>(P, sd, f_out);
     }
+}
+
+hipError_t launch_fused(const ProbDev &P, const StepDev &st, bool grad,
+                        float *f_out, hipStream_t stream) {
+    if (P.D == 5) launch_fused_t<true>(P, st, grad, f_out, stream);
+    else launch_fused_t<false>(P, st, grad, f_out, stream);
     return hipGetLastError();
 }
 

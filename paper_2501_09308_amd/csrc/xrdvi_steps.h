@@ -8,14 +8,14 @@ namespace xrdvi {
 
 // ---- a1: sample and transform ---------------------------------------------
 //
-// Block of 256 threads = 64 phases x 4 latent types of sample s, phases
-// kb*64 .. kb*64+63.  Each thread draws one coordinate
-// z = loc + exp(logscale) eps, maps it to its constrained value and adds
-// its log prior + log|dphi/dz| term; the first wave then writes the FP32
-// kernel constants and the block's sum of those terms.
+// Block of 256 threads = 64 phases x 4 of sample s, phases kb*64 .. kb*64+63;
+// the thread of type t draws latent types t and t + 4 (< D).  Each draw is
+// z = loc + exp(logscale) eps, mapped to its constrained value, with its
+// log prior + log|dphi/dz| term; the first wave then writes the FP32 kernel
+// constants and the block's sum of those terms.
 struct SampleSmem {
-    double val[4][kWave];
-    double lpt[4][kWave];
+    double val[5][kWave];
+    double lpt[5][kWave];
 };
 
 __device__ inline void sample_block(const ProbDev &P, const StepDev &st,
@@ -25,45 +25,61 @@ __device__ inline void sample_block(const ProbDev &P, const StepDev &st,
                                     uint64_t seed, uint64_t step, int s, int kb,
                                     int nkb, SampleSmem &sm) {
 #pragma clang fp contract(off)
-    const int t = threadIdx.x / kWave, kk = threadIdx.x % kWave;
+    const int t0 = threadIdx.x / kWave, kk = threadIdx.x % kWave;
     const int k = kb * kWave + kk;
-    const int K = P.K, D = 4 * K;
-    double v = 0.0, lp = 0.0;
-    if (k < K) {
-        const int j = t * K + k;
-        const double e = eps_in ? eps_in[(size_t)s * D + j]
-                                : philox_normal(seed, step, s, j);
-        const double sd = exp(logscale[j]);
-        const double dz = sd * e;
-        const double z = loc[j] + dz;
-        st.eps[(size_t)s * D + j] = e;
-        if (s == 0) st.sd[j] = sd;
-        if (t == 0) {            // h = e^z, h ~ Exp(lambda); |dh/dz| = h
-            v = exp(z);
-            lp = P.c_h - P.lambda * v + z;
-        } else if (t == 1) {     // mu = z, mu ~ N(0, mu_sd)
-            const double um = z / P.mu_sd;
-            v = z;
-            lp = P.c_mu - 0.5 * um * um;
-        } else if (t == 2) {     // w = e^z, w ~ Gamma(shape, rate); |dw/dz| = w
-            v = exp(z);
-            lp = P.c_w + (P.w_shape - 1.0) * z - P.w_rate * v + z;
-        } else {                 // r = logistic(z), r ~ U(0,1); |dr/dz| = r(1-r)
-            v = 1.0 / (1.0 + exp(-z));
-            lp = -softplus(-z) - softplus(z);
+    const int K = P.K, D = P.D * K;
+    for (int t = t0; t < P.D; t += 4) {
+        double v = 0.0, lp = 0.0;
+        if (k < K) {
+            const int j = t * K + k;
+            const double e = eps_in ? eps_in[(size_t)s * D + j]
+                                    : philox_normal(seed, step, s, j);
+            const double sd = exp(logscale[j]);
+            const double dz = sd * e;
+            const double z = loc[j] + dz;
+            st.eps[(size_t)s * D + j] = e;
+            if (s == 0) st.sd[j] = sd;
+            if (t == 0) {            // h = e^z, h ~ Exp(lambda); |dh/dz| = h
+                v = exp(z);
+                lp = P.c_h - P.lambda * v + z;
+            } else if (t == 1) {     // mu = z, mu ~ N(0, mu_sd)
+                const double um = z / P.mu_sd;
+                v = z;
+                lp = P.c_mu - 0.5 * um * um;
+            } else if (t == 2) {     // w = e^z, w ~ Gamma(shape, rate); |dw/dz| = w
+                v = exp(z);
+                lp = P.c_w + (P.w_shape - 1.0) * z - P.w_rate * v + z;
+            } else if (t == 3) {     // r = logistic(z), r ~ U(0,1); |dr/dz| = r(1-r)
+                v = 1.0 / (1.0 + exp(-z));
+                lp = -softplus(-z) - softplus(z);
+            } else {                 // alpha = e^z, alpha ~ N(a_mean, a_sd); |J| = alpha
+                v = exp(z);
+                const double ua = (v - P.a_mean) / P.a_sd;
+                lp = P.c_a - 0.5 * ua * ua + z;
+            }
+            st.phi[(size_t)s * D + j] = v;
         }
-        st.phi[(size_t)s * D + j] = v;
+        sm.val[t][kk] = v;
+        sm.lpt[t][kk] = lp;
     }
-    sm.val[t][kk] = v;
-    sm.lpt[t][kk] = lp;
     __syncthreads();
-    if (t == 0) {
+    if (t0 == 0) {
         double lpk = 0.0;
         if (k < K) {
-            st.pk[(size_t)s * K + k] = phase_consts(sm.val[0][kk], sm.val[1][kk],
-                                                    sm.val[2][kk], sm.val[3][kk]);
+            const size_t o = (size_t)s * K + k;
             lpk = sm.lpt[0][kk] + sm.lpt[1][kk] + sm.lpt[2][kk] + sm.lpt[3][kk];
-            st.lpj[(size_t)s * K + k] = lpk;
+            if (P.D == 5) {
+                const double al = sm.val[4][kk];
+                lpk += sm.lpt[4][kk];
+                st.pk[o] = phase_consts(sm.val[0][kk], sm.val[1][kk],
+                                        sm.val[2][kk], sm.val[3][kk],
+                                        asym_norm(al));
+                st.pkr[o] = asym_iw2(sm.val[2][kk], al);
+            } else {
+                st.pk[o] = phase_consts(sm.val[0][kk], sm.val[1][kk],
+                                        sm.val[2][kk], sm.val[3][kk]);
+            }
+            st.lpj[o] = lpk;
         }
         lpk = wave_sum(lpk);
         if (kk == 0) st.lpb[(size_t)s * nkb + kb] = lpk;
@@ -76,8 +92,9 @@ __device__ inline void windows_elem(const ProbDev &P, const double *phi,
                                     size_t g) {
     const int s = (int)(g / P.T), j = (int)(g % P.T);
     const int k = P.phase[j];
-    const double *ph = phi + (size_t)s * 4 * P.K;
-    const int2 wnd = window_of(P, P.pos[j], ph[P.K + k], ph[2 * P.K + k]);
+    const double *ph = phi + (size_t)s * P.D * P.K;
+    const int2 wnd = window_of(P, P.pos[j], ph[P.K + k], ph[2 * P.K + k],
+                               P.D == 5 ? ph[4 * P.K + k] : 1.0);
     const size_t o = (size_t)s * P.T + (perm ? perm[j] : j);
     lo[o] = wnd.x;
     hi[o] = wnd.y;
@@ -89,7 +106,13 @@ __device__ inline void plan_elem(const ProbDev &P, const StepDev &st,
     const int k = (int)(g % P.K);
     const size_t st_idx = g / P.K;
     const int t = (int)(st_idx % P.ntiles), s = (int)(st_idx / P.ntiles);
-    st.rng[g] = tile_range(P, st, phi, s, t, k);
+    if (P.D == 5) {
+        int2 side;
+        st.rng[g] = tile_range(P, st, phi, s, t, k, &side);
+        st.rng2[g] = side;
+    } else {
+        st.rng[g] = tile_range(P, st, phi, s, t, k, nullptr);
+    }
 }
 
 // ---- a5: ELBO assembly, block of 1024 threads --------------------------------
@@ -127,7 +150,7 @@ __device__ inline double elbo_block(const ProbDev &P, const StepDev &st,
         sm.tot[s] = l + p;
     }
     double ent = 0.0;
-    for (int j = tid; j < 4 * P.K; j += 1024) ent += logscale[j];
+    for (int j = tid; j < P.D * P.K; j += 1024) ent += logscale[j];
     ent = wave_sum(ent);
     if ((tid & (kWave - 1)) == 0) sm.red[tid / kWave] = ent;
     __syncthreads();
@@ -137,13 +160,13 @@ __device__ inline double elbo_block(const ProbDev &P, const StepDev &st,
     }
     double e = 0.0;
     for (int w = 0; w < 1024 / kWave; ++w) e += sm.red[w];
-    const double D = 4.0 * P.K;
+    const double D = (double)P.D * P.K;
     return sm.tot[0] / S + e + 0.5 * D * (1.0 + kLn2Pi);   // valid in all threads
 }
 
 // ---- a8: Adam (Kingma & Ba) ascent step on one coordinate --------------------
 struct AdamArgs {
-    double *m1_loc, *m2_loc, *m1_ls, *m2_ls;   // [4K] moment estimates
+    double *m1_loc, *m2_loc, *m1_ls, *m2_ls;   // [D K] moment estimates
     int t;                                      // 1-based step
     double lr, b1, b2, eps;
 };
@@ -165,11 +188,43 @@ __device__ inline void adam_update(double &theta, double &m1, double &m2,
 // a stripe of tiles (dense) or reading the phase's sums (windowed); stripes,
 // samples and tiles are combined in FP64 in fixed order, then the chain
 // rule runs through the prior, Jacobian and reparameterisation.  With
-// `adam`, the gradient of the phase's 8 parameters updates loc/logscale
+// `adam`, the gradient of the phase's 2 D parameters updates loc/logscale
 // in place instead of being stored.
 struct GradSmem {
-    double red[256][6];
+    double red[256][12];
 };
+
+// d lnL / d(h, mu, w, r[, alpha]) of one (sample, phase) from the adjoint
+// sums E (sums over points and peaks with R = (y/f - 1) I):
+//   E0 = sum R e, E1 = sum R e q2 / A, E2 = sum R e q2^2,
+//   L0 = sum R l, L1 = sum R l^2 q2 / A, L2 = sum R l^2,
+// and for asymmetric peaks the high-side parts E2u = sum_{x >= rho} R e q2^2
+// and Q2u = sum_{x >= rho} R l^2 q2^2 = sum_{x >= rho} R (l - l^2).
+__device__ inline void phase_grad(const ProbDev &P, const double *E, double h,
+                                  double w, double r, double alpha,
+                                  double g[5]) {
+#pragma clang fp contract(off)
+    double E0, E1, E2, L0, L1, L2, nrm = 1.0;
+    if (P.D == 5) {
+        const double ia = 1.0 / alpha;
+        E0 = E[0] + E[6];  E1 = E[1] + ia * E[7];  E2 = E[2] + E[8];
+        L0 = E[3] + E[9];  L1 = E[4] + ia * E[10]; L2 = E[5] + E[11];
+        nrm = asym_norm(alpha);
+    } else {
+        E0 = E[0]; E1 = E[1]; E2 = E[2]; L0 = E[3]; L1 = E[4]; L2 = E[5];
+    }
+    const double iw = 1.0 / w, iw2 = iw * iw;
+    const double cg = (1.0 - r) * kCG * nrm, cl = r * kCL * nrm;
+    g[0] = cg * iw * E0 + cl * iw * L0;
+    g[1] = h * iw2 * (cg * 4.0 * kLn2 * E1 + cl * 4.0 * L1);
+    g[2] = h * iw2 * (cg * (2.0 * kLn2 * E2 - E0) + cl * (L0 - 2.0 * L2));
+    g[3] = h * iw * nrm * (kCL * L0 - kCG * E0);
+    if (P.D == 5) {
+        const double E2u = E[8], Q2u = E[9] - E[11];
+        g[4] = h * iw * (-(cg * E0 + cl * L0) / (1.0 + alpha)
+                         + (cg * 2.0 * kLn2 * E2u + cl * 2.0 * Q2u) / alpha);
+    }
+}
 
 __device__ inline void grad_block(const ProbDev &P, const StepDev &st, int k,
                                   double scale, const double *scale_dev,
@@ -177,58 +232,59 @@ __device__ inline void grad_block(const ProbDev &P, const StepDev &st, int k,
                                   double *loc, double *logscale,
                                   const AdamArgs *adam, GradSmem &sm) {
 #pragma clang fp contract(off)
-    const int K = P.K, D = 4 * K, S = st.S;
+    const int K = P.K, D = P.D * K, S = st.S, NT = P.D;
+    const int NS = num_sums(P.D);
     const int SG = S < kWave ? S : kWave;
     const int G = 256 / SG;
     const int tid = threadIdx.x, sl = tid % SG, g = tid / SG;
-    double am[4] = {0, 0, 0, 0}, as[4] = {0, 0, 0, 0};
+    double am[5] = {0, 0, 0, 0, 0}, as[5] = {0, 0, 0, 0, 0};
     for (int s0 = 0; s0 < S; s0 += SG) {
         const int s = s0 + sl;
-        double E[6] = {0, 0, 0, 0, 0, 0};
+        // E stays in registers: every loop over it has a constant trip count
+        double E[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         if (g < G && s < S) {
             if (P.cutoff > 0.0) {
                 if (g == 0) {
-                    const double *src = st.pw + ((size_t)k * S + s) * 6;
+                    const double *src = st.pw + ((size_t)k * S + s) * NS;
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) E[c] = src[c];
+                    for (int c = 0; c < 12; ++c)
+                        if (c < NS) E[c] = src[c];
                 }
             } else {
                 for (int t = g; t < P.ntiles; t += G) {
-                    const float *src = st.part + (((size_t)t * K + k) * S + s) * 6;
+                    const float *src = st.part + (((size_t)t * K + k) * S + s) * NS;
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) E[c] += (double)src[c];
+                    for (int c = 0; c < 12; ++c)
+                        if (c < NS) E[c] += (double)src[c];
                 }
             }
         }
 #pragma unroll
-        for (int c = 0; c < 6; ++c) sm.red[tid][c] = E[c];
+        for (int c = 0; c < 12; ++c) sm.red[tid][c] = E[c];
         __syncthreads();
         if (g == 0 && s < S) {
 #pragma unroll
-            for (int c = 0; c < 6; ++c) E[c] = 0.0;
+            for (int c = 0; c < 12; ++c) E[c] = 0.0;
             for (int gg = 0; gg < G; ++gg)
 #pragma unroll
-                for (int c = 0; c < 6; ++c) E[c] += sm.red[gg * SG + sl][c];
+                for (int c = 0; c < 12; ++c) E[c] += sm.red[gg * SG + sl][c];
             const double *ph = st.phi + (size_t)s * D;
             const double h = ph[k], mu = ph[K + k], w = ph[2 * K + k],
                          r = ph[3 * K + k];
-            const double iw = 1.0 / w, iw2 = iw * iw;
-            // d lnL / d(h, mu, w, r) from the six sums
-            // E0 = sum R e, E1 = sum R e q2, E2 = sum R e q2^2,
-            // L0 = sum R l, L1 = sum R l^2 q2, L2 = sum R l^2, R = (y/f - 1) I
-            const double gh = (1.0 - r) * kCG * iw * E[0] + r * kCL * iw * E[3];
-            const double gmu = h * iw2 * ((1.0 - r) * kCG * 4.0 * kLn2 * E[1]
-                                          + r * kCL * 4.0 * E[4]);
-            const double gw = h * iw2 * ((1.0 - r) * kCG * (2.0 * kLn2 * E[2] - E[0])
-                                         + r * kCL * (E[3] - 2.0 * E[5]));
-            const double gr = h * iw * (kCL * E[3] - kCG * E[0]);
-            double gz[4];
-            gz[0] = h * gh - P.lambda * h + 1.0;
-            gz[1] = gmu - mu / (P.mu_sd * P.mu_sd);
-            gz[2] = w * gw + (P.w_shape - 1.0) - P.w_rate * w + 1.0;
-            gz[3] = r * (1.0 - r) * gr + 1.0 - 2.0 * r;
+            const double al = P.D == 5 ? ph[4 * K + k] : 1.0;
+            double gp[5];
+            phase_grad(P, E, h, w, r, al, gp);
+            double gz[5];
+            gz[0] = h * gp[0] - P.lambda * h + 1.0;
+            gz[1] = gp[1] - mu / (P.mu_sd * P.mu_sd);
+            gz[2] = w * gp[2] + (P.w_shape - 1.0) - P.w_rate * w + 1.0;
+            gz[3] = r * (1.0 - r) * gp[3] + 1.0 - 2.0 * r;
+            gz[4] = P.D == 5
+                ? al * gp[4] - al * (al - P.a_mean) / (P.a_sd * P.a_sd) + 1.0
+                : 0.0;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
+            for (int t = 0; t < 5; ++t) {
+                if (t >= NT) break;
                 const int j = t * K + k;
                 am[t] += gz[t];
                 as[t] += gz[t] * st.eps[(size_t)s * D + j] * st.sd[j];
@@ -238,14 +294,15 @@ __device__ inline void grad_block(const ProbDev &P, const StepDev &st, int k,
     }
     if (tid < kWave) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < 5; ++t) {
             am[t] = wave_sum(am[t]);
             as[t] = wave_sum(as[t]);
         }
         if (tid == 0) {
             if (scale_dev) scale *= *scale_dev;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
+            for (int t = 0; t < 5; ++t) {
+                if (t >= NT) break;
                 const int j = t * K + k;
                 const double gl = scale * (am[t] / S);
                 const double gs = scale * (as[t] / S + 1.0);

@@ -133,31 +133,33 @@ def poisson_counts(fstar: np.ndarray, seed: int) -> np.ndarray:
     return rng.poisson(np.asarray(fstar, dtype=np.float64)).astype(np.float64)
 
 
-def eps_draw(S: int, K: int, seed: int, step: int = 0) -> np.ndarray:
-    """Standard-normal reparameterisation noise [S][4][K] for one step."""
+def eps_draw(S: int, K: int, seed: int, step: int = 0, D: int = 4) -> np.ndarray:
+    """Standard-normal reparameterisation noise [S][D][K] for one step."""
     rng = np.random.default_rng([seed, step])
-    return rng.standard_normal((S, 4, K))
+    return rng.standard_normal((S, D, K))
 
 
-def random_params(K: int, seed: int, y_max: float, spread: float = 0.3):
-    """Variational parameters (loc, logscale) [4][K] scattered around the
+def random_params(K: int, seed: int, y_max: float, spread: float = 0.3,
+                  D: int = 4):
+    """Variational parameters (loc, logscale) [D][K] scattered around the
     default initialisation, for parity tests away from any optimum."""
     rng = np.random.default_rng(seed)
-    loc, logscale = init_params(K, y_max)
-    loc = loc + spread * rng.standard_normal((4, K))
-    logscale = logscale + spread * rng.standard_normal((4, K))
+    loc, logscale = init_params(K, y_max, D)
+    loc = loc + spread * rng.standard_normal((D, K))
+    logscale = logscale + spread * rng.standard_normal((D, K))
     return loc, logscale
 
 
-def init_params(K: int, y_max: float):
+def init_params(K: int, y_max: float, D: int = 4):
     """Default initial variational parameters (unconstrained space):
-    m_h = ln(0.01*y_max), m_mu = 0, m_w = ln 0.1, m_r = 0, omega = ln 0.1."""
-    loc = np.zeros((4, K))
+    m_h = ln(0.01*y_max), m_mu = 0, m_w = ln 0.1, m_r = 0 (and m_alpha = 0
+    when D = 5), omega = ln 0.1."""
+    loc = np.zeros((D, K))
     loc[0, :] = np.log(0.01 * y_max)
     loc[1, :] = 0.0
     loc[2, :] = np.log(0.1)
     loc[3, :] = 0.0
-    logscale = np.full((4, K), np.log(0.1))
+    logscale = np.full((D, K), np.log(0.1))
     return loc, logscale
 
 
@@ -178,3 +180,11 @@ def random_phi(K: int, S: int, seed: int, h_max: float = 2.0e4,
     phi[:, 2] = rng.uniform(w_range[0], w_range[1], (S, K))
     phi[:, 3] = rng.uniform(0.0, 1.0, (S, K))
     return phi
+
+
+def random_alpha(K: int, S: int, seed: int, lo: float = 0.6,
+                 hi: float = 1.8) -> np.ndarray:
+    """Asymmetries alpha [S][K] ~ U(lo, hi), to append to random_phi as the
+    fifth latent row."""
+    rng = np.random.default_rng([seed, 5])
+    return rng.uniform(lo, hi, (S, K))

@@ -34,7 +34,8 @@ class XrdviError(RuntimeError):
 
 class Prior(C.Structure):
     _fields_ = [("lambda_h", C.c_double), ("mu_sd", C.c_double),
-                ("w_shape", C.c_double), ("w_rate", C.c_double)]
+                ("w_shape", C.c_double), ("w_rate", C.c_double),
+                ("alpha_mean", C.c_double), ("alpha_sd", C.c_double)]
 
 
 class ProblemDesc(C.Structure):
@@ -44,7 +45,8 @@ class ProblemDesc(C.Structure):
                 ("peak_off", C.POINTER(C.c_int32)),
                 ("peak_pos", C.POINTER(C.c_double)),
                 ("peak_int", C.POINTER(C.c_double)),
-                ("cutoff", C.c_double), ("prior", Prior)]
+                ("cutoff", C.c_double), ("prior", Prior),
+                ("asymmetric", C.c_int32)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -155,7 +157,8 @@ def _dev_f64(t, shape, name):
 
 
 def make_desc(x, y, bg, peak_off, peak_pos, peak_int, cutoff=0.0,
-              lambda_h=0.0, mu_sd=0.03, w_shape=3.0, w_rate=100.0):
+              lambda_h=0.0, mu_sd=0.03, w_shape=3.0, w_rate=100.0,
+              asymmetric=False, alpha_mean=1.0, alpha_sd=0.2):
     """Builds a ProblemDesc over host arrays; returns (desc, keepalive)."""
     arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, bg)]
     off = np.ascontiguousarray(peak_off, dtype=np.int32)
@@ -171,7 +174,8 @@ def make_desc(x, y, bg, peak_off, peak_pos, peak_int, cutoff=0.0,
     d.peak_off = off.ctypes.data_as(C.POINTER(C.c_int32))
     d.peak_pos = pos.ctypes.data_as(P); d.peak_int = inten.ctypes.data_as(P)
     d.cutoff = float(cutoff)
-    d.prior = Prior(lambda_h, mu_sd, w_shape, w_rate)
+    d.prior = Prior(lambda_h, mu_sd, w_shape, w_rate, alpha_mean, alpha_sd)
+    d.asymmetric = 1 if asymmetric else 0
     return d, (arrs, off, pos, inten)
 
 
@@ -221,10 +225,11 @@ class Problem:
 
     def __init__(self, ctx: Context, x, y, bg, peak_off, peak_pos, peak_int,
                  cutoff=0.0, lambda_h=0.0, mu_sd=0.03, w_shape=3.0,
-                 w_rate=100.0):
+                 w_rate=100.0, asymmetric=False, alpha_mean=1.0, alpha_sd=0.2):
         self.ctx = ctx
         d, keep = make_desc(x, y, bg, peak_off, peak_pos, peak_int, cutoff,
-                            lambda_h, mu_sd, w_shape, w_rate)
+                            lambda_h, mu_sd, w_shape, w_rate, asymmetric,
+                            alpha_mean, alpha_sd)
         h = _VP()
         _check(ctx.lib.xrdvi_problem_create(ctx.handle, C.byref(d), C.byref(h)))
         self.handle = h
@@ -233,6 +238,7 @@ class Problem:
                                           C.byref(lam)))
         self.N, self.K, self.T, self.lambda_h = N.value, K.value, T.value, lam.value
         self.cutoff = float(cutoff)
+        self.D = 5 if asymmetric else 4     # latent types per phase
 
     @classmethod
     def from_workload(cls, ctx, prob, y, **kw):
@@ -281,11 +287,11 @@ def xrdvi_tape_create(ctx, prob, S) -> Tape:
 
 def xrdvi_profile(ctx: Context, prob: Problem, phi: torch.Tensor,
                   out: torch.Tensor | None = None) -> torch.Tensor:
-    """f[S][N] (float32) at constrained phi[S][4][K] (float64, device)."""
+    """f[S][N] (float32) at constrained phi[S][D][K] (float64, device)."""
     if phi.dim() == 2:
         phi = phi.unsqueeze(0)
     S = phi.shape[0]
-    phi = _dev_f64(phi, (S, 4, prob.K), "phi")
+    phi = _dev_f64(phi, (S, prob.D, prob.K), "phi")
     if out is None:
         out = torch.empty((S, prob.N), dtype=torch.float32, device=phi.device)
     _check(ctx.lib.xrdvi_profile(ctx.handle, prob.handle, S, _ptr(phi), _ptr(out),
@@ -298,7 +304,7 @@ def xrdvi_window_plan(ctx: Context, prob: Problem, phi: torch.Tensor):
     if phi.dim() == 2:
         phi = phi.unsqueeze(0)
     S = phi.shape[0]
-    phi = _dev_f64(phi, (S, 4, prob.K), "phi")
+    phi = _dev_f64(phi, (S, prob.D, prob.K), "phi")
     lo = torch.empty((S, max(prob.T, 1)), dtype=torch.int32, device=phi.device)
     hi = torch.empty_like(lo)
     _check(ctx.lib.xrdvi_window_plan(ctx.handle, prob.handle, S, _ptr(phi),
@@ -310,11 +316,11 @@ def xrdvi_elbo_fwd(ctx: Context, prob: Problem, tape: Tape, loc, logscale,
                    eps=None, seed=0, step=0, need_grad=True, elbo_out=None,
                    loglik_out=None):
     """Returns (elbo [1], loglik [S]) float64 device tensors."""
-    K, S = prob.K, tape.S
-    loc = _dev_f64(loc, (4, K), "loc")
-    logscale = _dev_f64(logscale, (4, K), "logscale")
+    K, S, D = prob.K, tape.S, prob.D
+    loc = _dev_f64(loc, (D, K), "loc")
+    logscale = _dev_f64(logscale, (D, K), "logscale")
     if eps is not None:
-        eps = _dev_f64(eps, (S, 4, K), "eps")
+        eps = _dev_f64(eps, (S, D, K), "eps")
     dev = loc.device
     if elbo_out is None:
         elbo_out = torch.empty(1, dtype=torch.float64, device=dev)
@@ -330,9 +336,9 @@ def xrdvi_elbo_fwd(ctx: Context, prob: Problem, tape: Tape, loc, logscale,
 
 
 def xrdvi_tape_samples(ctx: Context, tape: Tape, out=None):
-    """Constrained samples [S][4][K] of the last forward on `tape`."""
+    """Constrained samples [S][D][K] of the last forward on `tape`."""
     if out is None:
-        out = torch.empty((tape.S, 4, tape.prob.K), dtype=torch.float64,
+        out = torch.empty((tape.S, tape.prob.D, tape.prob.K), dtype=torch.float64,
                           device=torch.device("cuda", ctx.device))
     _check(ctx.lib.xrdvi_tape_samples(ctx.handle, tape.handle, _ptr(out),
                                       _stream(out.device)))
@@ -342,12 +348,12 @@ def xrdvi_tape_samples(ctx: Context, tape: Tape, out=None):
 def xrdvi_elbo_bwd(ctx: Context, tape: Tape, grad_scale=1.0,
                    grad_scale_dev: torch.Tensor | None = None,
                    grad_loc=None, grad_logscale=None, device=None):
-    K = tape.prob.K
+    K, D = tape.prob.K, tape.prob.D
     dev = device if device is not None else torch.device("cuda", ctx.device)
     if grad_loc is None:
-        grad_loc = torch.empty((4, K), dtype=torch.float64, device=dev)
+        grad_loc = torch.empty((D, K), dtype=torch.float64, device=dev)
     if grad_logscale is None:
-        grad_logscale = torch.empty((4, K), dtype=torch.float64, device=dev)
+        grad_logscale = torch.empty((D, K), dtype=torch.float64, device=dev)
     if grad_scale_dev is not None:
         grad_scale_dev = grad_scale_dev.to(torch.float64).contiguous()
     _check(ctx.lib.xrdvi_elbo_bwd(ctx.handle, tape.handle, float(grad_scale),
@@ -409,8 +415,9 @@ class _Submission:
         self.desc, self.keep = make_desc(x, y, bg, peak_off, peak_pos,
                                          peak_int, cutoff, **prior)
         K = len(peak_off) - 1
-        self.loc = np.zeros((4, K))
-        self.logscale = np.zeros((4, K))
+        D = 5 if prior.get("asymmetric") else 4
+        self.loc = np.zeros((D, K))
+        self.logscale = np.zeros((D, K))
         self.trace = np.zeros(int(steps))
         self.init = None
         if init is not None:

@@ -32,6 +32,15 @@ def _args(**over):
 
 def test_validate_accepts_good_problem():
     assert X.xrdvi_validate(**_args()) == 0
+    assert X.xrdvi_validate(**_args(asymmetric=True)) == 0
+
+
+def test_validate_rejects_unknown_asymmetry_flag():
+    d, keep = X.make_desc(**_args())
+    d.asymmetric = 2
+    lib = X.load()
+    assert lib.xrdvi_validate(C.byref(d)) == X.XRDVI_EINVAL
+    assert b"asymmetric" in lib.xrdvi_last_error()
 
 
 @pytest.mark.parametrize("mutate,msg", [
@@ -47,6 +56,8 @@ def test_validate_accepts_good_problem():
     (lambda a: a.update(mu_sd=0.0), "mu_sd"),
     (lambda a: a.update(w_rate=-1.0), "w_rate"),
     (lambda a: a.update(peak_pos=np.full_like(a["peak_pos"], np.nan)), "finite"),
+    (lambda a: a.update(asymmetric=True, alpha_sd=0.0), "alpha_sd"),
+    (lambda a: a.update(asymmetric=True, alpha_mean=np.inf), "alpha_mean"),
 ])
 def test_validate_rejects(mutate, msg):
     a = _args()
