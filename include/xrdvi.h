@@ -310,6 +310,30 @@ XRDVI_API int xrdvi_tape_samples(xrdvi_ctx *ctx, const xrdvi_tape *tape,
                                  double *phi_out, void *stream);
 
 /*
+ * Posterior readout of a converged analysis (Sec. 4: phases are identified
+ * by their area ratio, with a threshold of 1 %).  Under q the weight h_k is
+ * log-normal, so with m = loc[0][k] and s = exp(logscale[0][k]):
+ *   E_q[h_k] = exp(m + s^2/2),  sd_q[h_k] = E_q[h_k] sqrt(exp(s^2) - 1).
+ * Peaks have unit area, so phase k's area is E_q[h_k] sum_m I_m; its ratio
+ * is that area over the sum of all phases' areas, and selected[k] = 1 when
+ * the ratio exceeds `threshold`.  Host arrays only; no GPU work.
+ *   K, peak_off[K+1], peak_int[T]  the candidate set, as in the problem
+ *                                  description
+ *   loc_h, logscale_h              host double [K]: row 0 (h) of loc and
+ *                                  logscale, e.g. a served request's output
+ *   threshold                      in [0, 1) (0.01 in the paper)
+ *   mean_h, sd_h, area_ratio       host double [K], each may be NULL
+ *   selected                       host int32 [K] or NULL
+ * XRDVI_EINVAL for malformed arguments or a total area that is not
+ * positive and finite.
+ */
+XRDVI_API int xrdvi_readout(int32_t K, const int32_t *peak_off,
+                            const double *peak_int, const double *loc_h,
+                            const double *logscale_h, double threshold,
+                            double *mean_h, double *sd_h, double *area_ratio,
+                            int32_t *selected);
+
+/*
  * Kernel timing for measurement: while enabled, every fused profile /
  * likelihood / adjoint launch issued through `ctx` is bracketed by HIP
  * events recorded on the launch's own stream.  xrdvi_timing_read waits for

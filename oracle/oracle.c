@@ -570,6 +570,36 @@ int oracle_elbo_asym(int N, int K, const double *x, const double *y,
     return 0;
 }
 
+/* ---- posterior readout (Sec. 4: selection by area ratio) -------------- */
+
+/*
+ * With h = exp(z), z ~ N(m, s^2) under q: E[h] = exp(m + s^2/2) and
+ * sd[h] = E[h] sqrt(exp(s^2) - 1) (log-normal moments).  Unit-area peaks
+ * make phase k's area E[h_k] sum_m I_m; ratio = area / total area;
+ * selected = ratio > threshold.  Returns -1 when the total is not positive.
+ */
+int oracle_readout(int K, const int *peak_off, const double *I,
+                   const double *m, const double *logscale, double threshold,
+                   double *mean_h, double *sd_h, double *ratio, int *selected)
+{
+    double total = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double s = exp(logscale[k]);
+        mean_h[k] = exp(m[k] + 0.5 * s * s);
+        sd_h[k] = mean_h[k] * sqrt(exp(s * s) - 1.0);
+        double isum = 0.0;
+        for (int j = peak_off[k]; j < peak_off[k + 1]; ++j) isum += I[j];
+        ratio[k] = mean_h[k] * isum;
+        total += ratio[k];
+    }
+    if (!(total > 0.0)) return -1;
+    for (int k = 0; k < K; ++k) {
+        ratio[k] /= total;
+        selected[k] = ratio[k] > threshold;
+    }
+    return 0;
+}
+
 /* ---- Adam (Kingma & Ba 2015) on the maximisation of the ELBO ----------- */
 
 /* One ascent step on theta with gradient g; m1, m2 are the moment

@@ -57,6 +57,8 @@ def load():
     lib.oracle_eps_philox.argtypes = [C.c_int, C.c_int, C.c_uint64,
                                       C.c_uint64, _D]
     lib.oracle_eps_philox_n.argtypes = lib.oracle_eps_philox.argtypes
+    lib.oracle_readout.argtypes = [C.c_int, _I, _D, _D, _D, C.c_double,
+                                   _D, _D, _D, _I]
     lib.oracle_num_threads.restype = C.c_int
     lib.oracle_profile_asym.argtypes = lib.oracle_profile.argtypes
     lib.oracle_windows_asym.argtypes = lib.oracle_windows.argtypes
@@ -236,6 +238,23 @@ def elbo_asym(prob, y, loc, logscale, eps, *, lam=0.0, mu_sd=0.03,
     if rc != 0:
         raise ValueError(f"oracle_elbo_asym failed: {rc}")
     return out.value, ll, (gl if grad else None), (gs if grad else None)
+
+
+def readout(peak_off, peak_int, m_h, logscale_h, threshold=0.01):
+    """(mean_h, sd_h, area_ratio, selected indices) of the h latent."""
+    lib = load()
+    K = len(peak_off) - 1
+    keep = [_i(peak_off), _d(peak_int if len(peak_int) else [0.0]), _d(m_h),
+            _d(logscale_h)]
+    mean, sd, ratio = np.empty(K), np.empty(K), np.empty(K)
+    sel = np.empty(K, dtype=np.int32)
+    rc = lib.oracle_readout(K, keep[0][1], keep[1][1], keep[2][1], keep[3][1],
+                            float(threshold), mean.ctypes.data_as(_D),
+                            sd.ctypes.data_as(_D), ratio.ctypes.data_as(_D),
+                            sel.ctypes.data_as(_I))
+    if rc != 0:
+        raise ValueError("oracle_readout: total area not positive")
+    return mean, sd, ratio, np.nonzero(sel)[0]
 
 
 def num_threads():

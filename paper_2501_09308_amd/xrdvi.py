@@ -121,6 +121,8 @@ def load():
         "xrdvi_server_clock": ([_VP], C.c_double),
         "xrdvi_plain_run": ([_VP, C.POINTER(Request), C.POINTER(Status), _VP],
                             C.c_int),
+        "xrdvi_readout": ([i32, _VP, _VP, _VP, _VP, dbl, _VP, _VP, _VP, _VP],
+                          C.c_int),
         "xrdvi_timing_enable": ([_VP, i32], C.c_int),
         "xrdvi_timing_read": ([_VP, C.POINTER(dbl), C.POINTER(C.c_int64), i32],
                               C.c_int),
@@ -514,3 +516,25 @@ def xrdvi_plain_run(ctx: Context, prob, y, S, steps, seed, lr=0.0, init=None,
                                    _stream()))
     return dict(loc=sub.loc, logscale=sub.logscale, trace=sub.trace,
                 final_elbo=st.final_elbo)
+
+
+def xrdvi_readout(peak_off, peak_int, loc, logscale, threshold=0.01):
+    """Posterior readout (host): dict(mean_h, sd_h, area_ratio, selected)
+    from the h rows of (loc, logscale)."""
+    off = np.ascontiguousarray(peak_off, dtype=np.int32)
+    inten = np.ascontiguousarray(peak_int, dtype=np.float64)
+    if inten.size == 0:
+        inten = np.zeros(1)
+    K = len(off) - 1
+    m = np.ascontiguousarray(np.asarray(loc)[0], dtype=np.float64)
+    s = np.ascontiguousarray(np.asarray(logscale)[0], dtype=np.float64)
+    if m.shape != (K,) or s.shape != (K,):
+        raise ValueError(f"loc and logscale must have K={K} columns")
+    out = {k: np.empty(K) for k in ("mean_h", "sd_h", "area_ratio")}
+    sel = np.empty(K, dtype=np.int32)
+    P = lambda a: a.ctypes.data_as(C.c_void_p)
+    _check(load().xrdvi_readout(K, P(off), P(inten), P(m), P(s),
+                                float(threshold), P(out["mean_h"]),
+                                P(out["sd_h"]), P(out["area_ratio"]), P(sel)))
+    out["selected"] = np.nonzero(sel)[0]
+    return out

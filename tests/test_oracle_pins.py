@@ -16,6 +16,8 @@ from scipy import special, stats
 
 from paper_2501_09308_amd import workloads as W
 
+from selection_common import map_support, phase_basis
+
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -346,52 +348,6 @@ def test_gradient_vanishes_at_noise_free_truth(orc):
 
 # ---- selection: brute force over all 2^K phase subsets ---------------------
 
-def _map_support(C, y, B, lam):
-    """Exact MAP of h >= 0 for f = B + C^T h, objective
-    sum(y ln f - f) - lam sum h (concave), by enumerating supports and
-    solving each with damped Newton (step halving keeps f > 0 and the
-    objective increasing)."""
-    K = C.shape[0]
-
-    def objective(CT, hT):
-        f = B + CT.T @ hT
-        if np.any(f <= 0):
-            return -np.inf
-        return np.sum(special.xlogy(y, f) - f) - lam * hT.sum()
-
-    best = (-np.inf, None, None)
-    for mask in range(1 << K):
-        T = [k for k in range(K) if mask >> k & 1]
-        h = np.zeros(K)
-        if T:
-            CT = C[T]
-            hT = np.full(len(T), 100.0)
-            cur = objective(CT, hT)
-            for _ in range(500):
-                f = B + CT.T @ hT
-                g = CT @ (y / f - 1) - lam
-                H = -(CT * (y / f ** 2)) @ CT.T
-                step = np.linalg.solve(H, -g)
-                t = 1.0
-                while t > 1e-12:
-                    new = objective(CT, hT + t * step)
-                    if new >= cur:
-                        break
-                    t *= 0.5
-                hT = hT + t * step
-                cur = objective(CT, hT)
-                if np.max(np.abs(t * step)) < 1e-11 * max(1.0, np.max(np.abs(hT))):
-                    break
-            if np.any(hT <= 0):
-                continue
-            h[T] = hT
-        f = B + C.T @ h
-        obj = np.sum(special.xlogy(y, f) - f) - lam * h.sum()
-        if obj > best[0]:
-            best = (obj, h, T)
-    return best
-
-
 def test_bruteforce_subset_map(orc):
     prob = W.make_problem("tiny", seed=1003, K=8, M=20)
     phi = prob.phi_true.copy()
@@ -400,19 +356,12 @@ def test_bruteforce_subset_map(orc):
         if k not in prob.true_idx:
             phi[1:, k] = [0.0, 0.1, 0.5]
     K = prob.K
-    basis_phi = np.zeros((K, 4, K))
-    for k in range(K):
-        basis_phi[k] = phi
-        basis_phi[k, 0] = 0.0
-        basis_phi[k, 0, k] = 1.0
-    zero = np.zeros(prob.N)
-    C = orc.profile(prob.x, zero, prob.peak_off, prob.peak_pos, prob.peak_int,
-                    0.0, basis_phi)
+    C = phase_basis(orc, prob, phi)
     fstar = orc.profile(prob.x, prob.bg, prob.peak_off, prob.peak_pos,
                         prob.peak_int, 0.0, phi)[0]
     y = W.poisson_counts(fstar, 77)
     lam = 1 / (y - prob.bg).max()
-    obj, hmap, T = _map_support(C, y, prob.bg, lam)
+    obj, hmap, T = map_support(C, y, prob.bg, lam)
     # selection by area ratio above 1 % (Sec. 4): a phase's area is
     # h_k sum_m I_m for unit-area peaks; it recovers the generating phases
     area = np.array([hmap[k] * prob.peak_int[prob.peak_off[k]:prob.peak_off[k + 1]].sum()
