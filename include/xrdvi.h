@@ -133,6 +133,10 @@ XRDVI_API int xrdvi_problem_info(const xrdvi_problem *prob, int32_t *N,
                                  int32_t *K, int32_t *total_peaks,
                                  double *lambda_h);
 
+/* Latent types per phase of a problem: 4, or 5 for asymmetric peaks (D in
+ * the array shapes below); negative (XRDVI_EINVAL) for NULL. */
+XRDVI_API int xrdvi_problem_latents(const xrdvi_problem *prob);
+
 /* Per-step device state for S samples of one problem: noise, samples,
  * window plan and the adjoint's per-tile partial sums (never the S x K x N
  * peak basis).  Holds the saved state between xrdvi_elbo_fwd and
@@ -308,6 +312,62 @@ XRDVI_API int xrdvi_plain_run(xrdvi_ctx *ctx, const xrdvi_request *req,
  */
 XRDVI_API int xrdvi_tape_samples(xrdvi_ctx *ctx, const xrdvi_tape *tape,
                                  double *phi_out, void *stream);
+
+/*
+ * Unnormalised log posterior density in the unconstrained coordinates and
+ * its gradient, at S positions (Sec. 3.2 transforms; App. A.2 likelihood;
+ * Sec. 2.2 and App. B.2 priors):
+ *   logp_s = ln p(Y | phi(z_s)) + ln p(phi(z_s)) + ln|d phi / d z|(z_s)
+ *   grad_s = d logp_s / d z_s
+ * computed by the same fused forward and adjoint kernels as the ELBO (the
+ * ELBO estimate is the mean of logp over its samples plus the entropy).
+ *   z         device double [S][D][K] positions (rows as loc)
+ *   logp_out  device double [S]
+ *   grad_out  device double [S][D][K], or NULL for the density only
+ *   tape      created for this problem with the same S (its ELBO state is
+ *             overwritten: a later xrdvi_elbo_bwd needs a new forward)
+ */
+XRDVI_API int xrdvi_logpost(xrdvi_ctx *ctx, const xrdvi_problem *prob,
+                            int32_t S, const double *z, double *logp_out,
+                            double *grad_out, xrdvi_tape *tape, void *stream);
+
+/*
+ * Hamiltonian Monte Carlo over the same posterior (the sampling method the
+ * paper compares stochastic VI with: 1000 samples after 1000 burn-in
+ * iterations, Sec. 4 and Table 1).  Every gradient is one xrdvi_logpost
+ * evaluation of all chains together.  Iteration i of chain c draws its
+ * momentum p ~ N(0, I) from Philox4x32-10 keyed by (seed, i) (counter
+ * (j/4, c, i), Box-Muller as for the ELBO noise), takes n_leapfrog leapfrog
+ * steps, and accepts with probability min(1, exp(H0 - H1)),
+ * H = -logp + |p|^2 / 2, using u = (v0 + 0.5) / 2^32 of the Philox block
+ * with counter (0, c, i) and key seed ^ 0x9E3779B97F4A7C15.  During the
+ * n_warmup iterations each chain adapts its step size by dual averaging
+ * (Hoffman and Gelman 2014: mu = ln(10 step_size), gamma = 0.05, t0 = 10,
+ * kappa = 0.75, target acceptance target_accept), then keeps the averaged
+ * step for the n_draws kept iterations.  A non-finite Hamiltonian is a
+ * rejection.  Synchronous.
+ *   z           device double [chains][D][K]: initial positions in, final
+ *               positions out
+ *   draws       device double [n_draws][chains][D][K] or NULL
+ *   logp_draws  device double [n_draws][chains] or NULL
+ *   accept_out  host double [chains]: acceptance rate of the kept
+ *               iterations, or NULL
+ *   step_out    host double [chains]: final step sizes, or NULL
+ */
+typedef struct {
+    int32_t chains;        /* 1..1024 */
+    int32_t n_warmup;      /* >= 0 */
+    int32_t n_draws;       /* >= 0 */
+    int32_t n_leapfrog;    /* >= 1 */
+    double step_size;      /* initial step size, > 0 */
+    double target_accept;  /* in (0, 1); 0 selects 0.8 */
+    uint64_t seed;
+} xrdvi_hmc_config;
+
+XRDVI_API int xrdvi_hmc(xrdvi_ctx *ctx, const xrdvi_problem *prob,
+                        const xrdvi_hmc_config *cfg, double *z, double *draws,
+                        double *logp_draws, double *accept_out,
+                        double *step_out, void *stream);
 
 /*
  * Posterior readout of a converged analysis (Sec. 4: phases are identified

@@ -37,6 +37,7 @@ struct xrdvi_tape {
     int device = 0;           // destroy never dereferences prob
     StepDev st{};
     void *mem = nullptr;
+    double *zeros = nullptr;  // D K zeros (mean and log-scale of a position)
     bool has_grad = false;
 };
 
@@ -435,6 +436,11 @@ int xrdvi_problem_info(const xrdvi_problem *prob, int32_t *N, int32_t *K,
     return XRDVI_OK;
 }
 
+int xrdvi_problem_latents(const xrdvi_problem *prob) {
+    if (!prob) return fail(XRDVI_EINVAL, "problem is NULL");
+    return prob->P.D;
+}
+
 int xrdvi_tape_create(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
                       xrdvi_tape **out) {
     API_GUARD_BEGIN
@@ -443,15 +449,20 @@ int xrdvi_tape_create(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     DeviceGuard g(ctx->device);
     const ProbDev &P = prob->P;
     const size_t bytes = step_bytes(step_shape(P, S));
+    const size_t zbytes = sizeof(double) * P.D * (size_t)P.K;
     void *mem = nullptr;
-    hipError_t e = hipMalloc(&mem, bytes);
-    if (e != hipSuccess)
+    hipError_t e = hipMalloc(&mem, bytes + zbytes);
+    if (e == hipSuccess) e = hipMemset(static_cast<char *>(mem) + bytes, 0, zbytes);
+    if (e != hipSuccess) {
+        if (mem) (void)hipFree(mem);
         return fail(XRDVI_ENOMEM, std::string("tape allocation: ") + hipGetErrorString(e));
+    }
     auto *t = new xrdvi_tape();
     t->prob = prob;
     t->device = ctx->device;
     t->mem = mem;
     t->st = carve_step(mem, step_shape(P, S));
+    t->zeros = reinterpret_cast<double *>(static_cast<char *>(mem) + bytes);
     *out = t;
     return XRDVI_OK;
     API_GUARD_END
@@ -547,6 +558,24 @@ int xrdvi_elbo_bwd(xrdvi_ctx *ctx, const xrdvi_tape *tape, double grad_scale,
                         grad_loc, grad_logscale,
                         static_cast<hipStream_t>(stream)),
             "gradient");
+    return XRDVI_OK;
+    API_GUARD_END
+}
+
+int xrdvi_logpost(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
+                  const double *z, double *logp_out, double *grad_out,
+                  xrdvi_tape *tape, void *stream) {
+    API_GUARD_BEGIN
+    if (!ctx || !prob || !z || !logp_out || !tape)
+        return fail(XRDVI_EINVAL, "NULL argument");
+    if (prob->ctx != ctx) return fail(XRDVI_EINVAL, "problem belongs to another context");
+    if (tape->prob != prob) return fail(XRDVI_EINVAL, "tape belongs to another problem");
+    if (S != tape->st.S) return fail(XRDVI_EINVAL, "S differs from the tape's S");
+    DeviceGuard g(ctx->device);
+    tape->has_grad = false;
+    HIP_TRY(launch_logpost(prob->P, tape->st, tape->zeros, z, logp_out, grad_out,
+                           static_cast<hipStream_t>(stream)),
+            "log posterior");
     return XRDVI_OK;
     API_GUARD_END
 }

@@ -26,12 +26,22 @@ hipError_t launch_plan(const ProbDev &P, const StepDev &st, const double *phi,
                        hipStream_t stream);
 hipError_t launch_fused(const ProbDev &P, const StepDev &st, bool grad,
                         float *f_out, hipStream_t stream);
+// logp_out: per-sample log posterior density; gz_out: per-sample gradient
+// of it in z, [S][D K] (both optional).
 hipError_t launch_elbo(const ProbDev &P, const StepDev &st,
                        const double *logscale, double *elbo_out,
-                       double *loglik_out, hipStream_t stream);
+                       double *loglik_out, hipStream_t stream,
+                       double *logp_out = nullptr);
 hipError_t launch_grad(const ProbDev &P, const StepDev &st, double scale,
                        const double *scale_dev, double *gloc,
-                       double *glogscale, hipStream_t stream);
+                       double *glogscale, hipStream_t stream,
+                       double *gz_out = nullptr);
+
+// Per-sample log posterior density and (gz != NULL) its gradient in z at
+// positions z [S][D K]; zeros: D K zeros.
+hipError_t launch_logpost(const ProbDev &P, const StepDev &st,
+                          const double *zeros, const double *z, double *logp,
+                          double *gz, hipStream_t stream);
 
 hipError_t launch_adam(int n, double *theta, double *m1, double *m2,
                        const double *g, int t, double lr, double b1, double b2,

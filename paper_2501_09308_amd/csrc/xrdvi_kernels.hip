@@ -95,10 +95,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_win(ProbDev P, StepDev st) {
 __global__ __launch_bounds__(1024) void k_elbo(ProbDev P, StepDev st,
                                                const double *__restrict__ logscale,
                                                double *elbo_out,
-                                               double *loglik_out) {
+                                               double *loglik_out,
+                                               double *logp_out) {
     __shared__ ElboSmem sm;
-    const double e = elbo_block(P, st, logscale, loglik_out, sm);
-    if (threadIdx.x == 0) *elbo_out = e;
+    const double e = elbo_block(P, st, logscale, loglik_out, sm, logp_out);
+    if (threadIdx.x == 0 && elbo_out) *elbo_out = e;
 }
 
 // a7: one block of 256 threads per phase.
@@ -106,10 +107,11 @@ __global__ __launch_bounds__(256) void k_grad(ProbDev P, StepDev st,
                                               double scale,
                                               const double *scale_dev,
                                               double *gloc,
-                                              double *glogscale) {
+                                              double *glogscale,
+                                              double *gz_out) {
     __shared__ GradSmem sm;
     grad_block(P, st, blockIdx.x, scale, scale_dev, gloc, glogscale, nullptr,
-               nullptr, nullptr, sm);
+               nullptr, nullptr, sm, gz_out);
 }
 
 // a8: Adam ascent step on n coordinates.
@@ -199,15 +201,19 @@ hipError_t launch_fused(const ProbDev &P, const StepDev &st, bool grad,
 
 hipError_t launch_elbo(const ProbDev &P, const StepDev &st,
                        const double *logscale, double *elbo_out,
-                       double *loglik_out, hipStream_t stream) {
-    k_elbo<<<1, 1024, 0, stream>>>(P, st, logscale, elbo_out, loglik_out);
+                       double *loglik_out, hipStream_t stream,
+                       double *logp_out) {
+    k_elbo<<<1, 1024, 0, stream>>>(P, st, logscale, elbo_out, loglik_out,
+                                   logp_out);
     return hipGetLastError();
 }
 
 hipError_t launch_grad(const ProbDev &P, const StepDev &st, double scale,
                        const double *scale_dev, double *gloc,
-                       double *glogscale, hipStream_t stream) {
-    k_grad<<<P.K, 256, 0, stream>>>(P, st, scale, scale_dev, gloc, glogscale);
+                       double *glogscale, hipStream_t stream,
+                       double *gz_out) {
+    k_grad<<<P.K, 256, 0, stream>>>(P, st, scale, scale_dev, gloc, glogscale,
+                                    gz_out);
     return hipGetLastError();
 }
 
@@ -217,6 +223,29 @@ hipError_t launch_adam(int n, double *theta, double *m1, double *m2,
     k_adam<<<(n + 255) / 256, 256, 0, stream>>>(n, theta, m1, m2, g, t, lr, b1,
                                                  b2, eps);
     return hipGetLastError();
+}
+
+}  // namespace xrdvi
+
+namespace xrdvi {
+
+// Log posterior density ln p(Y|phi) + ln p(phi) + ln|J| and its gradient in
+// z at the positions z [S][D K] (one per sample): the sampling step with a
+// zero mean and unit scale reproduces z exactly, the rest is the ELBO
+// step's fused forward, adjoint and chain rule, with per-sample outputs.
+hipError_t launch_logpost(const ProbDev &P, const StepDev &st,
+                          const double *zeros, const double *z, double *logp,
+                          double *gz, hipStream_t stream) {
+    hipError_t e = launch_sample(P, st, zeros, zeros, z, 0, 0, stream);
+    if (e == hipSuccess && P.cutoff > 0.0)
+        e = launch_windows(P, st.S, st.phi, st.lo, st.hi, nullptr, stream);
+    if (e == hipSuccess) e = launch_plan(P, st, st.phi, stream);
+    if (e == hipSuccess) e = launch_fused(P, st, gz != nullptr, nullptr, stream);
+    if (e == hipSuccess)
+        e = launch_elbo(P, st, zeros, nullptr, nullptr, stream, logp);
+    if (e == hipSuccess && gz)
+        e = launch_grad(P, st, 1.0, nullptr, nullptr, nullptr, stream, gz);
+    return e;
 }
 
 }  // namespace xrdvi

@@ -125,9 +125,12 @@ struct ElboSmem {
     double red[1024 / kWave];
 };
 
+// logp_out (may be NULL) receives each sample's ln p(Y|phi_s) + ln p(phi_s)
+// + ln|J(z_s)|: the unnormalised log posterior density at z_s.
 __device__ inline double elbo_block(const ProbDev &P, const StepDev &st,
                                     const double *__restrict__ logscale,
-                                    double *loglik_out, ElboSmem &sm) {
+                                    double *loglik_out, ElboSmem &sm,
+                                    double *logp_out = nullptr) {
 #pragma clang fp contract(off)
     const int S = st.S;
     int G = 1;
@@ -147,6 +150,7 @@ __device__ inline double elbo_block(const ProbDev &P, const StepDev &st,
     __syncthreads();
     if (g == 0 && s < S) {
         if (loglik_out) loglik_out[s] = l;
+        if (logp_out) logp_out[s] = l + p;
         sm.tot[s] = l + p;
     }
     double ent = 0.0;
@@ -189,7 +193,8 @@ __device__ inline void adam_update(double &theta, double &m1, double &m2,
 // samples and tiles are combined in FP64 in fixed order, then the chain
 // rule runs through the prior, Jacobian and reparameterisation.  With
 // `adam`, the gradient of the phase's 2 D parameters updates loc/logscale
-// in place instead of being stored.
+// in place instead of being stored.  gz_out (may be NULL) receives every
+// sample's gradient of the log posterior density in z, [S][D K].
 struct GradSmem {
     double red[256][12];
 };
@@ -230,7 +235,8 @@ __device__ inline void grad_block(const ProbDev &P, const StepDev &st, int k,
                                   double scale, const double *scale_dev,
                                   double *gloc, double *glogscale,
                                   double *loc, double *logscale,
-                                  const AdamArgs *adam, GradSmem &sm) {
+                                  const AdamArgs *adam, GradSmem &sm,
+                                  double *gz_out = nullptr) {
 #pragma clang fp contract(off)
     const int K = P.K, D = P.D * K, S = st.S, NT = P.D;
     const int NS = num_sums(P.D);
@@ -286,6 +292,7 @@ __device__ inline void grad_block(const ProbDev &P, const StepDev &st, int k,
             for (int t = 0; t < 5; ++t) {
                 if (t >= NT) break;
                 const int j = t * K + k;
+                if (gz_out) gz_out[(size_t)s * D + j] = gz[t];
                 am[t] += gz[t];
                 as[t] += gz[t] * st.eps[(size_t)s * D + j] * st.sd[j];
             }
@@ -311,7 +318,7 @@ __device__ inline void grad_block(const ProbDev &P, const StepDev &st, int k,
                                 adam->t, adam->lr, adam->b1, adam->b2, adam->eps);
                     adam_update(logscale[j], adam->m1_ls[j], adam->m2_ls[j], gs,
                                 adam->t, adam->lr, adam->b1, adam->b2, adam->eps);
-                } else {
+                } else if (gloc) {
                     gloc[j] = gl;
                     glogscale[j] = gs;
                 }

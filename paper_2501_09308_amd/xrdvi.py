@@ -72,6 +72,13 @@ class ServerConfig(C.Structure):
                 ("arena_bytes", C.c_size_t)]
 
 
+class HmcConfig(C.Structure):
+    _fields_ = [("chains", C.c_int32), ("n_warmup", C.c_int32),
+                ("n_draws", C.c_int32), ("n_leapfrog", C.c_int32),
+                ("step_size", C.c_double), ("target_accept", C.c_double),
+                ("seed", C.c_uint64)]
+
+
 _lib = None
 _VP = C.c_void_p
 
@@ -123,6 +130,10 @@ def load():
                             C.c_int),
         "xrdvi_readout": ([i32, _VP, _VP, _VP, _VP, dbl, _VP, _VP, _VP, _VP],
                           C.c_int),
+        "xrdvi_problem_latents": ([_VP], C.c_int),
+        "xrdvi_logpost": ([_VP, _VP, i32, _VP, _VP, _VP, _VP, _VP], C.c_int),
+        "xrdvi_hmc": ([_VP, _VP, C.POINTER(HmcConfig), _VP, _VP, _VP, _VP, _VP,
+                       _VP], C.c_int),
         "xrdvi_timing_enable": ([_VP, i32], C.c_int),
         "xrdvi_timing_read": ([_VP, C.POINTER(dbl), C.POINTER(C.c_int64), i32],
                               C.c_int),
@@ -538,3 +549,40 @@ def xrdvi_readout(peak_off, peak_int, loc, logscale, threshold=0.01):
                                 P(out["sd_h"]), P(out["area_ratio"]), P(sel)))
     out["selected"] = np.nonzero(sel)[0]
     return out
+
+
+def xrdvi_logpost(ctx: Context, prob: Problem, tape: Tape, z, grad=True):
+    """(logp [S], grad [S][D][K] or None) at positions z [S][D][K]."""
+    S = tape.S
+    z = _dev_f64(z, (S, prob.D, prob.K), "z")
+    logp = torch.empty(S, dtype=torch.float64, device=z.device)
+    g = torch.empty_like(z) if grad else None
+    _check(ctx.lib.xrdvi_logpost(ctx.handle, prob.handle, S, _ptr(z), _ptr(logp),
+                                 _ptr(g), tape.handle, _stream(z.device)))
+    tape.version += 1
+    return logp, g
+
+
+def xrdvi_hmc(ctx: Context, prob: Problem, z, n_warmup, n_draws, n_leapfrog,
+              step_size, seed, target_accept=0.8, keep_draws=True):
+    """Hamiltonian Monte Carlo from positions z [chains][D][K] (a contiguous
+    float64 CUDA tensor, updated in place to the final positions).
+    Returns dict(draws [n_draws][chains][D][K] or None, logp
+    [n_draws][chains], accept [chains], step [chains])."""
+    nc = z.shape[0]
+    if not (isinstance(z, torch.Tensor) and z.is_cuda and z.dtype == torch.float64
+            and z.is_contiguous() and tuple(z.shape) == (nc, prob.D, prob.K)):
+        raise ValueError(f"z must be a contiguous float64 CUDA tensor of shape "
+                         f"({nc}, {prob.D}, {prob.K})")
+    cfg = HmcConfig(nc, int(n_warmup), int(n_draws), int(n_leapfrog),
+                    float(step_size), float(target_accept), int(seed))
+    draws = (torch.empty((n_draws, nc, prob.D, prob.K), dtype=torch.float64,
+                         device=z.device) if keep_draws and n_draws else None)
+    logp = torch.empty((max(n_draws, 1), nc), dtype=torch.float64, device=z.device)
+    acc = np.zeros(nc)
+    step = np.zeros(nc)
+    _check(ctx.lib.xrdvi_hmc(ctx.handle, prob.handle, C.byref(cfg), _ptr(z),
+                             _ptr(draws), _ptr(logp),
+                             acc.ctypes.data_as(C.c_void_p),
+                             step.ctypes.data_as(C.c_void_p), _stream(z.device)))
+    return dict(draws=draws, logp=logp[:n_draws], accept=acc, step=step)
