@@ -128,6 +128,51 @@ def run_cpu(W, prob, y, S_total, target_s=12.0):
                         f"(S={S_total}, c=0; {pts:.3g} peak-points, {dt:.1f} s)"))
 
 
+def run_background(X, W, ctx, prob, lam=1e7, p=0.001, n_iter=15):
+    """Device asymmetric-least-squares background of the bench
+    diffractogram (one spectrum) and of a batch of 64 such spectra."""
+    import torch
+    _, y = gpu_problem(X, W, ctx, prob, 0.0)
+    one = torch.as_tensor(y, device="cuda")
+    batch = one.repeat(64, 1).contiguous()
+    out = {}
+    for name, t in (("one_spectrum_ms", one), ("batch64_ms", batch)):
+        X.xrdvi_background(ctx, t, lam, p, n_iter)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X.xrdvi_background(ctx, t, lam, p, n_iter)
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0) * 1e3
+    out.update(N=int(prob.N), lam=lam, p=p, iterations=n_iter)
+    return out
+
+
+def run_hmc(X, W, ctx, prob, chains=8, warm=1000, keep=1000, leapfrog=10):
+    """The shape of the paper's SVI-vs-MCMC comparison on this GPU: 1000
+    SVI steps (S=64, one analysis at a time) against Hamiltonian Monte Carlo
+    with 1000 warm-up and 1000 kept iterations on the same problem."""
+    import torch
+    P, y = gpu_problem(X, W, ctx, prob, 0.0)
+    ymax = float((y - prob.bg).max())
+    loc, _ = W.init_params(P.K, ymax)
+    z = torch.as_tensor(np.repeat(loc[None], chains, axis=0), device="cuda").contiguous()
+    X.xrdvi_hmc(ctx, P, z, 5, 5, 2, 1e-5, 1)          # warm the code paths
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = X.xrdvi_hmc(ctx, P, z, warm, keep, leapfrog, 1e-5, SEED,
+                      keep_draws=False)
+    torch.cuda.synchronize()
+    hmc_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    X.xrdvi_plain_run(ctx, prob, y, 64, 1000, SEED)
+    svi_s = time.perf_counter() - t0
+    return dict(svi_1000_steps_s=svi_s, hmc_s=hmc_s, chains=chains,
+                warmup=warm, draws=keep, leapfrog=leapfrog,
+                gradient_evals=(warm + keep) * leapfrog,
+                mean_accept=float(np.mean(out["accept"])),
+                ratio_hmc_over_svi=hmc_s / svi_s)
+
+
 def serving_requests(X, W, ctx, n, seed):
     """The serving mix: n requests (N, step, K, peaks per phase drawn per
     request, windows at 8 FWHM) with counts drawn around the HIP profile
@@ -223,6 +268,8 @@ def main(argv=None):
     ap.add_argument("--serving-steps", type=int, default=300)
     ap.add_argument("--serving-rate", type=float, default=40.0)
     ap.add_argument("--max-slots", type=int, default=128)
+    ap.add_argument("--no-hmc", dest="hmc", action="store_false",
+                    help="skip the SVI-vs-HMC timing")
     ap.add_argument("--steps-per-launch", type=int, default=10)
     a = ap.parse_args(argv)
     if a.gpus != 1:
@@ -254,6 +301,15 @@ def main(argv=None):
     asym = run_gpu(X, W, ctx, prob, S, 0.0, a.steps, a.warmup, False,
                    asymmetric=True)
     log(f"[bench] asymmetric done: {asym['wall_s'] / a.steps * 1e3:.3f} ms/step")
+
+    log("[bench] background (asymmetric least squares)")
+    bg_ctx = run_background(X, W, ctx, prob)
+
+    hmc_ctx = None
+    if a.hmc:
+        log("[bench] hmc: 1000 warm-up + 1000 kept iterations")
+        hmc_ctx = run_hmc(X, W, ctx, prob)
+        log(f"[bench] hmc done: {hmc_ctx['hmc_s']:.2f} s")
 
     ms_step = dense["wall_s"] / a.steps * 1e3
     value = sum(dense["points"]) / dense["wall_s"]
@@ -306,6 +362,8 @@ def main(argv=None):
             "latents_per_phase": 5,
         },
         "context_1000_steps_s": ms_step,   # 1000 steps x ms/step / 1000
+        "svi_vs_hmc": hmc_ctx,
+        "background": bg_ctx,
         "paper_context": {
             "svi_full_analysis_s": 7.2,
             "hardware": "Tesla V100S-PCIE-32GB",
@@ -313,6 +371,7 @@ def main(argv=None):
                          "2-theta 10-60 deg step 0.02 (N=2501), 1000 SVI "
                          "steps; peaks per phase and S not stated"),
             "note": "context only: a different workload and machine",
+            "mcmc_full_analysis_s": 1326.9,
         },
     }
     if a.serving > 0:

@@ -370,6 +370,28 @@ XRDVI_API int xrdvi_hmc(xrdvi_ctx *ctx, const xrdvi_problem *prob,
                         double *step_out, void *stream);
 
 /*
+ * Background estimate before an analysis (App. A.2: the background is
+ * estimated beforehand by an iterative least-squares method), by asymmetric
+ * least squares (Eilers and Boelens 2005): starting from w = 1, n_iter
+ * times solve (W + lambda D^T D) z = W y (D the second-difference
+ * operator, W = diag(w)) and set w_i = p where y_i > z_i and 1 - p elsewhere;
+ * the last z is the background.  FP64, one thread per spectrum, LDL^T of the
+ * pentadiagonal system.
+ *   B, N      spectra and points per spectrum (>= 1)
+ *   y         device double [B][N] counts
+ *   lambda    smoothness (>= 0; e.g. 1e5 - 1e8 for 2-theta steps of 0.01 -
+ *             0.02 deg); p in (0, 0.5) (e.g. 0.001 - 0.05)
+ *   bg_out    device double [B][N] (may not alias y)
+ *   scratch   device memory of 4 B N doubles, owned by the caller
+ * The result can be <= 0 where counts are low; a problem description needs
+ * bg > 0, so clamp it before xrdvi_problem_create.
+ */
+XRDVI_API int xrdvi_background(xrdvi_ctx *ctx, int32_t B, int32_t N,
+                               const double *y, double lambda, double p,
+                               int32_t n_iter, double *bg_out, void *scratch,
+                               void *stream);
+
+/*
  * Posterior readout of a converged analysis (Sec. 4: phases are identified
  * by their area ratio, with a threshold of 1 %).  Under q the weight h_k is
  * log-normal, so with m = loc[0][k] and s = exp(logscale[0][k]):

@@ -131,6 +131,8 @@ def load():
         "xrdvi_readout": ([i32, _VP, _VP, _VP, _VP, dbl, _VP, _VP, _VP, _VP],
                           C.c_int),
         "xrdvi_problem_latents": ([_VP], C.c_int),
+        "xrdvi_background": ([_VP, i32, i32, _VP, dbl, dbl, i32, _VP, _VP, _VP],
+                             C.c_int),
         "xrdvi_logpost": ([_VP, _VP, i32, _VP, _VP, _VP, _VP, _VP], C.c_int),
         "xrdvi_hmc": ([_VP, _VP, C.POINTER(HmcConfig), _VP, _VP, _VP, _VP, _VP,
                        _VP], C.c_int),
@@ -586,3 +588,18 @@ def xrdvi_hmc(ctx: Context, prob: Problem, z, n_warmup, n_draws, n_leapfrog,
                              acc.ctypes.data_as(C.c_void_p),
                              step.ctypes.data_as(C.c_void_p), _stream(z.device)))
     return dict(draws=draws, logp=logp[:n_draws], accept=acc, step=step)
+
+
+def xrdvi_background(ctx: Context, y, lam=1e6, p=0.01, n_iter=10):
+    """Asymmetric-least-squares background of spectra y [B][N] (or [N]),
+    float64 CUDA tensor; returns a tensor of the same shape."""
+    squeeze = y.dim() == 1
+    y2 = y.unsqueeze(0) if squeeze else y
+    B, N = y2.shape
+    y2 = _dev_f64(y2, (B, N), "y")
+    out = torch.empty_like(y2)
+    scratch = torch.empty(4 * B * N, dtype=torch.float64, device=y2.device)
+    _check(ctx.lib.xrdvi_background(ctx.handle, B, N, _ptr(y2), float(lam),
+                                    float(p), int(n_iter), _ptr(out),
+                                    _ptr(scratch), _stream(y2.device)))
+    return out[0] if squeeze else out
