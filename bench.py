@@ -194,14 +194,16 @@ def pct(v, q):
     return float(np.percentile(np.asarray(v), q))
 
 
-def run_serving(X, W, ctx, n, rate, steps, S, seed, max_slots, per_launch):
+def run_serving(X, W, ctx, n, rate, steps, S, seed, max_slots, per_launch,
+                plain_leg=True, resident_mb=0.0):
     """Continuous batching vs one analysis at a time on the same arrival
     trace; returns both summaries."""
     reqs = serving_requests(X, W, ctx, n, seed)
     arrivals = W.arrival_times(n, rate, seed)
     # ---- served
     srv = X.Server(max_slots=max_slots, steps_per_launch=per_launch,
-                   use_graph=True, arena_bytes=24 << 30)
+                   use_graph=True, arena_bytes=24 << 30,
+                   resident_bytes=int(resident_mb * (1 << 20)))
     tickets, results = [], {}
     t0 = time.perf_counter()
     nxt = 0
@@ -226,8 +228,10 @@ def run_serving(X, W, ctx, n, rate, steps, S, seed, max_slots, per_launch):
     span = max(i["t_done"] for i in infos) - min(i["t_arrive"] for i in infos)
     served = dict(analyses_per_s=n / span, p50_s=pct(ttr, 50), p99_s=pct(ttr, 99),
                   makespan_s=span, max_slots=max_slots,
-                  steps_per_graph_replay=per_launch)
+                  resident_mb=resident_mb, steps_per_graph_replay=per_launch)
     log(f"[bench] served: {served}")
+    if not plain_leg:
+        return dict(served=served)
     # ---- plain: one at a time, per-step launches, same kernels and noise keys
     done, ttr_p = [], []
     t0 = time.perf_counter()
@@ -267,9 +271,14 @@ def main(argv=None):
                     help="analyses in the serving comparison (0 = skip)")
     ap.add_argument("--serving-steps", type=int, default=300)
     ap.add_argument("--serving-rate", type=float, default=40.0)
-    ap.add_argument("--max-slots", type=int, default=128)
+    ap.add_argument("--max-slots", type=int, default=16)
+    ap.add_argument("--resident-mb", type=float, default=0.0,
+                    help="cap on the resident analyses' summed footprint")
     ap.add_argument("--no-hmc", dest="hmc", action="store_false",
                     help="skip the SVI-vs-HMC timing")
+    ap.add_argument("--no-serving-plain", dest="serving_plain",
+                    action="store_false",
+                    help="serve only (skip the one-at-a-time comparison)")
     ap.add_argument("--steps-per-launch", type=int, default=10)
     a = ap.parse_args(argv)
     if a.gpus != 1:
@@ -378,7 +387,8 @@ def main(argv=None):
         log(f"[bench] serving: {a.serving} analyses")
         out["serving"] = run_serving(X, W, ctx, a.serving, a.serving_rate,
                                      a.serving_steps, 32, 4000, a.max_slots,
-                                     a.steps_per_launch)
+                                     a.steps_per_launch, a.serving_plain,
+                                     a.resident_mb)
     if rank == 0 and not a.no_cpu:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = run_cpu(W, prob, dense["y"], S)

@@ -270,6 +270,10 @@ typedef struct {
     void *arena;               /* device memory for resident analyses, or
                                   NULL to let the server allocate it         */
     size_t arena_bytes;
+    size_t resident_bytes;     /* > 0: cap on the summed footprint of the
+                                  resident analyses (one is always admitted
+                                  when none is resident); 0: no cap beyond
+                                  max_slots and the arena                    */
 } xrdvi_server_config;
 
 /* Creates a server with its own stream (default priority) and scheduler

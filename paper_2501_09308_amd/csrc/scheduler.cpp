@@ -66,10 +66,11 @@ size_t ArenaAllocator::free_bytes() const {
 // ---- scheduler ------------------------------------------------------------
 
 Scheduler::Scheduler(Executor *ex, size_t arena_bytes, int max_slots,
-                     int max_queue, int steps_per_run)
+                     int max_queue, int steps_per_run, size_t resident_bytes)
     : ex_(ex), arena_(arena_bytes), max_slots_(max_slots),
       max_queue_(max_queue), steps_per_run_(steps_per_run),
-      slot_used_(max_slots, 0), t0_(steady_seconds()) {
+      resident_limit_(resident_bytes), slot_used_(max_slots, 0),
+      t0_(steady_seconds()) {
     worker_ = std::thread([this] { loop(); });
 }
 
@@ -153,6 +154,7 @@ int Scheduler::take_slot() {
 // Called with the lock held, after the executor has released the job.
 void Scheduler::complete(Job *j, int state) {
     arena_.free(j->arena_off, j->bytes);
+    resident_ -= j->bytes;
     if (j->slot >= 0) slot_used_[j->slot] = 0;
     j->slot = -1;
     j->active = false;
@@ -187,12 +189,17 @@ void Scheduler::loop() {
             lk.lock();
             complete(j, kECanceled);
         }
-        // admit in arrival order while a slot and memory are free
+        // admit in arrival order while a slot, arena memory and the
+        // resident budget allow
         while (!queue_.empty() && (int)active_.size() < max_slots_) {
             Job *j = queue_.front();
+            if (resident_limit_ > 0 && !active_.empty() &&
+                resident_ + j->bytes > resident_limit_)
+                break;
             size_t off = 0;
             if (!arena_.alloc(j->bytes, &off)) break;
             queue_.pop_front();
+            resident_ += j->bytes;
             j->slot = take_slot();
             j->arena_off = off;
             j->t_admit = now();

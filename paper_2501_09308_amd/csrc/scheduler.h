@@ -92,8 +92,12 @@ struct JobStatus {
 
 class Scheduler {
   public:
+    // resident_bytes > 0 caps the summed footprint of the resident analyses
+    // (one analysis is always admitted when none is resident): on MI355X a
+    // batched step over a working set that fits the last-level caches runs
+    // faster than one spread over many more analyses.
     Scheduler(Executor *ex, size_t arena_bytes, int max_slots, int max_queue,
-              int steps_per_run);
+              int steps_per_run, size_t resident_bytes = 0);
     ~Scheduler();
 
     // Codes follow the C ABI: 0 ok, -1 invalid, -2 never fits, -4 busy.
@@ -114,6 +118,7 @@ class Scheduler {
     Executor *ex_;
     ArenaAllocator arena_;
     int max_slots_, max_queue_, steps_per_run_;
+    size_t resident_limit_ = 0, resident_ = 0;
     std::mutex mu_;
     std::condition_variable cv_;
     std::deque<Job *> queue_;

@@ -359,7 +359,8 @@ int xrdvi_server_create(const xrdvi_server_config *cfg, xrdvi_server **out) {
     }
     srv->sched = std::make_unique<Scheduler>(srv->ex.get(), cfg->arena_bytes,
                                              cfg->max_slots, cfg->max_queue,
-                                             cfg->steps_per_launch);
+                                             cfg->steps_per_launch,
+                                             cfg->resident_bytes);
     *out = srv.release();
     return XRDVI_OK;
     API_GUARD_END

@@ -69,7 +69,7 @@ class ServerConfig(C.Structure):
     _fields_ = [("device", C.c_int32), ("max_slots", C.c_int32),
                 ("max_queue", C.c_int32), ("steps_per_launch", C.c_int32),
                 ("use_graph", C.c_int32), ("arena", C.c_void_p),
-                ("arena_bytes", C.c_size_t)]
+                ("arena_bytes", C.c_size_t), ("resident_bytes", C.c_size_t)]
 
 
 class HmcConfig(C.Structure):
@@ -459,9 +459,9 @@ def _request_args(prob, y, S, steps, seed, lr=0.0, init=None, cutoff=None,
 class Server:
     """xrdvi_server: continuous batching of whole analyses (see xrdvi.h)."""
 
-    def __init__(self, device=0, max_slots=64, max_queue=1 << 16,
+    def __init__(self, device=0, max_slots=16, max_queue=1 << 16,
                  steps_per_launch=10, use_graph=True, arena=None,
-                 arena_bytes=None):
+                 arena_bytes=None, resident_bytes=0):
         self.lib = load()
         cfg = ServerConfig()
         cfg.device, cfg.max_slots, cfg.max_queue = device, max_slots, max_queue
@@ -472,6 +472,7 @@ class Server:
         else:
             cfg.arena = None
             cfg.arena_bytes = int(arena_bytes or (8 << 30))
+        cfg.resident_bytes = int(resident_bytes)
         self._arena = arena
         h = _VP()
         _check(self.lib.xrdvi_server_create(C.byref(cfg), C.byref(h)))

@@ -30,6 +30,9 @@ class FakeExecutor : public Executor {
     }
     int run(const std::vector<Job *> &active, int steps, bool changed) override {
         max_active_ = std::max<int>(max_active_, (int)active.size());
+        size_t resident = 0;
+        for (const Job *j : active) resident += footprint(*j);
+        max_resident_ = std::max(max_resident_, resident);
         ++runs_;
         // the resident set as (slot, ticket): any difference from the last
         // run must be announced, or the executor would keep stale work
@@ -54,6 +57,7 @@ class FakeExecutor : public Executor {
     }
     void release(Job &) override {}
     int max_active_ = 0, runs_ = 0, used_slots_ = 0;
+    size_t max_resident_ = 0;
     int missed_changes_ = 0, changed_runs_ = 0;
     std::vector<std::pair<int, uint64_t>> last_;
 
@@ -70,13 +74,23 @@ struct Fake {
 
 extern "C" {
 
-void *fake_create(size_t arena, int max_slots, int max_queue, int steps_per_run,
-                  int sleep_us) {
+void *fake_create_budget(size_t arena, int max_slots, int max_queue,
+                         int steps_per_run, int sleep_us, size_t resident) {
     auto *f = new Fake();
     f->ex = std::make_unique<FakeExecutor>(sleep_us);
     f->sched = std::make_unique<Scheduler>(f->ex.get(), arena, max_slots, max_queue,
-                                           steps_per_run);
+                                           steps_per_run, resident);
     return f;
+}
+
+void *fake_create(size_t arena, int max_slots, int max_queue, int steps_per_run,
+                  int sleep_us) {
+    return fake_create_budget(arena, max_slots, max_queue, steps_per_run,
+                              sleep_us, 0);
+}
+
+size_t fake_max_resident(void *h) {
+    return static_cast<Fake *>(h)->ex->max_resident_;
 }
 
 int fake_submit(void *h, int K, int N, int steps, uint64_t seed, double *out_loc,

@@ -36,13 +36,23 @@ def lib():
     l.fake_stats.argtypes = [C.c_void_p] + [C.POINTER(C.c_int)] * 3
     l.fake_destroy.argtypes = [C.c_void_p]
     l.fake_changes.argtypes = [C.c_void_p] + [C.POINTER(C.c_int)] * 2
+    l.fake_create_budget.restype = C.c_void_p
+    l.fake_create_budget.argtypes = [C.c_size_t, C.c_int, C.c_int, C.c_int,
+                                     C.c_int, C.c_size_t]
+    l.fake_max_resident.restype = C.c_size_t
+    l.fake_max_resident.argtypes = [C.c_void_p]
     return l
 
 
 class Fake:
-    def __init__(self, lib, arena=1 << 20, slots=4, queue=1000, steps=5, sleep_us=200):
+    def __init__(self, lib, arena=1 << 20, slots=4, queue=1000, steps=5, sleep_us=200,
+                 resident=None):
         self.lib = lib
-        self.h = lib.fake_create(arena, slots, queue, steps, sleep_us)
+        if resident is None:
+            self.h = lib.fake_create(arena, slots, queue, steps, sleep_us)
+        else:
+            self.h = lib.fake_create_budget(arena, slots, queue, steps, sleep_us,
+                                            resident)
         self.bufs = {}
 
     def submit(self, K=8, N=100, steps=20, seed=1):
@@ -232,3 +242,27 @@ def test_scheduler_stress_under_sanitizers():
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120, env=env)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "ok=" in r.stdout
+
+
+def test_resident_budget_caps_the_working_set(lib):
+    # each job K=8, N=100 occupies 8*1024 + 1600 = 9792 bytes (256-byte
+    # rounding aside); a budget of 2.5 jobs keeps at most 2 resident even
+    # with 8 free slots, and every job still completes
+    fp = 8 * 1024 + 100 * 16
+    f = Fake(lib, slots=8, steps=4, sleep_us=100, resident=int(2.5 * fp))
+    ts = [f.submit(steps=12, seed=i)[1] for i in range(10)]
+    res = f.wait(ts)
+    assert all(r[0] == OK for r in res.values())
+    assert lib.fake_max_resident(f.h) <= int(2.5 * fp)
+    assert f.stats()[0] == 2
+    f.close()
+
+
+def test_resident_budget_admits_one_oversized_job(lib):
+    fp = 8 * 1024 + 100 * 16
+    f = Fake(lib, slots=4, steps=4, sleep_us=100, resident=fp // 2)
+    ts = [f.submit(steps=8, seed=i)[1] for i in range(3)]
+    res = f.wait(ts)
+    assert all(r[0] == OK for r in res.values())
+    assert f.stats()[0] == 1
+    f.close()
