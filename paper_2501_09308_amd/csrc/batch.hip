@@ -8,6 +8,8 @@
 // single-analysis kernels, and the noise of step n of an analysis is keyed
 // by (its seed, n), so an analysis computes the same result alone or in
 // any mix.
+#include <type_traits>
+
 #include "batch.h"
 #include "xrdvi_steps.h"
 
@@ -117,8 +119,9 @@ __global__ __launch_bounds__(256) void kb_plan(const SlotDev *tab,
 template <bool WIN, bool ASYM>
 __global__ __launch_bounds__(kBlock) void kb_fused(const SlotDev *tab,
                                                    const SchedDev *sch) {
+    using Smem = typename std::conditional<WIN, WinTileSmem, FusedSmem>::type;
     __shared__ PrefixSmem ps;
-    __shared__ FusedSmem sm;
+    __shared__ Smem sm;
     load_prefix(sch, fused_kind(WIN, ASYM), ps);
     const int total = uniform(ps.pre[ps.n]);
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
@@ -129,7 +132,12 @@ __global__ __launch_bounds__(kBlock) void kb_fused(const SlotDev *tab,
         const int t = local % d.P.ntiles, s = local / d.P.ntiles;
         if (s >= d.st.S) continue;
         // windowed: forward only (the adjoint is peak-major); dense: fused
-        fused_tile<WIN, !WIN, ASYM>(d.P, d.st, t, s, nullptr, sm);
+        if constexpr (WIN) {
+            if (d.P.K >= kWinStageK) win_tile<ASYM>(d.P, d.st, t, s, nullptr, sm.w);
+            else fused_tile<true, false, ASYM>(d.P, d.st, t, s, nullptr, sm.f);
+        } else {
+            fused_tile<false, true, ASYM>(d.P, d.st, t, s, nullptr, sm);
+        }
         __syncthreads();
     }
 }

@@ -350,10 +350,31 @@ struct PeakMask {
 };
 
 // Per-peak data of one phase seen by a segment loop.
+// One peak as a segment loop sees it: tile-relative position, intensity
+// and (windowed mode) its grid window [lo, hi).
+struct PeakRec {
+    float pt, I;
+    int lo, hi;
+};
+
 struct SegPeaks {
     cptr<float> pt;       // tile-relative positions
     cptr<float> inten;
     cptr<int> wlo, whi;   // windows (WIN)
+    // scalar loads (unused fields are never loaded)
+    __device__ __forceinline__ PeakRec rec(int j) const {
+        return PeakRec{pt[j], inten[j], wlo[j], whi[j]};
+    }
+};
+
+// Peak records staged in LDS by the windowed tile (record j at pd[j + shift]).
+struct LdsPeaks {
+    const float4 *pd;
+    int shift;
+    __device__ __forceinline__ PeakRec rec(int j) const {
+        const float4 v = pd[j + shift];
+        return PeakRec{v.x, v.y, __float_as_int(v.z), __float_as_int(v.w)};
+    }
 };
 
 // Side of a segment: the points lie below the peak centres (or the peaks are
@@ -371,8 +392,8 @@ __device__ __forceinline__ float seg_q2(float ptj, float iw2, float iw2r,
     return ql >= 0.f ? qr : ql;
 }
 
-template <bool WIN, bool GAUSS, int SIDE>
-__device__ __forceinline__ void fwd_segment(const SegPeaks &pk, int j0, int j1,
+template <bool WIN, bool GAUSS, int SIDE, typename PK>
+__device__ __forceinline__ void fwd_segment(const PK &pk, int j0, int j1,
                                             const int (&idx)[kPPL],
                                             const float (&uq)[kPPL],
                                             const float (&uqr)[kPPL],
@@ -381,10 +402,11 @@ __device__ __forceinline__ void fwd_segment(const SegPeaks &pk, int j0, int j1,
                                             float (&accG)[kPPL]) {
 #pragma unroll 2
     for (int j = j0; j < j1; ++j) {
-        const float ptj = pk.pt[j];
-        const float I = pk.inten[j];
+        const PeakRec r = pk.rec(j);
+        const float ptj = r.pt;
+        const float I = r.I;
         PeakMask<WIN> mk;
-        if (WIN) { mk.lo = pk.wlo[j]; mk.hi = pk.whi[j]; }
+        if (WIN) { mk.lo = r.lo; mk.hi = r.hi; }
 #pragma unroll
         for (int p = 0; p < kPPL; ++p) {
             const float q2 = seg_q2<SIDE>(ptj, iw2, iw2r, uq[p], uqr[p]);
@@ -491,6 +513,44 @@ __device__ __forceinline__ void store_sums(const Acc6 &a,
     }
 }
 
+// Point stage of a tile, after the waves' partial signals are in sig:
+// f = B + signal in FP64, the tile's Poisson log-likelihood (to st.llp) and
+// the residual y/f - 1 (to rres_lds, and to st.rres when it is set).
+__device__ __forceinline__ void tile_points(const ProbDev &P, const StepDev &st,
+                                            int t, int s, float *f_out,
+                                            const float (*sig)[kTile],
+                                            float *rres_lds, double *red) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int i0 = t * kTile;
+    double ll = 0.0;
+    for (int q = threadIdx.x; q < kTile; q += kBlock) {
+        const int i = i0 + q;
+        float rr = 0.f;
+        if (i < P.N) {
+            double sg = 0.0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) sg += (double)sig[w][q];
+            const double f = P.bg[i] + sg;
+            if (f_out) f_out[(size_t)s * P.N + i] = (float)f;
+            const double y = P.y[i];
+            ll += (y != 0.0 ? y * log(f) : 0.0) - f - P.lgy[i];
+            rr = (float)(y / f - 1.0);
+            if (st.rres) st.rres[(size_t)s * P.N + i] = rr;
+        }
+        rres_lds[q] = rr;
+    }
+    ll = wave_sum(ll);
+    if (lane == 0) red[wv] = ll;
+    __syncthreads();
+    if (threadIdx.x == 0 && st.llp) {
+        double tot = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) tot += red[w];
+        st.llp[(size_t)s * P.ntiles + t] = tot;
+    }
+}
+
 template <bool WIN, bool GRAD, bool ASYM>
 __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
                            float *f_out, FusedSmem &sm) {
@@ -564,33 +624,7 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
     for (int p = 0; p < kPPL; ++p) sm.sig[wv][p * kWave + lane] = sig[p];
     __syncthreads();
 
-    // ---------------- point stage: f = B + signal (FP64), likelihood, residual
-    double ll = 0.0;
-    for (int q = threadIdx.x; q < kTile; q += kBlock) {
-        const int i = i0 + q;
-        float rr = 0.f;
-        if (i < P.N) {
-            double sg = 0.0;
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) sg += (double)sm.sig[w][q];
-            const double f = P.bg[i] + sg;
-            if (f_out) f_out[(size_t)s * P.N + i] = (float)f;
-            const double y = P.y[i];
-            ll += (y != 0.0 ? y * log(f) : 0.0) - f - P.lgy[i];
-            rr = (float)(y / f - 1.0);
-            if (st.rres) st.rres[(size_t)s * P.N + i] = rr;
-        }
-        sm.rres[q] = rr;
-    }
-    ll = wave_sum(ll);
-    if (lane == 0) sm.red[wv] = ll;
-    __syncthreads();
-    if (threadIdx.x == 0 && st.llp) {
-        double tot = 0.0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) tot += sm.red[w];
-        st.llp[(size_t)s * P.ntiles + t] = tot;
-    }
+    tile_points(P, st, t, s, f_out, sm.sig, sm.rres, sm.red);
     if (!GRAD) return;
 
     // ---------------- adjoint: recompute every peak value; the phase's sums
@@ -637,6 +671,161 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
     }
 }
 
+// ---- windowed forward tile with LDS-staged peak lists ----------------------
+//
+// In windowed mode only a few peaks of each phase reach a tile, so fetching
+// each phase's range and then its peaks one dependent load at a time would
+// leave the waves waiting.  The block instead stages, 256 phases at a time,
+// every phase's range and constants and the records (position, intensity,
+// window) of all peaks that reach the tile in LDS, with all threads loading
+// in parallel; the waves then walk their phases from LDS.  A chunk whose
+// peaks exceed the staging capacity reads the overflow with scalar loads.
+constexpr int kWinChunk = kBlock;   // phases staged at a time (one per thread)
+constexpr int kWinPeaks = 1024;     // staged peak records per chunk
+// Staging pays for its barriers and prefix sum only with many phases per
+// tile: from this K on the windowed forward stages (12000 points, K = 300,
+// S = 32: 105 us instead of 135 us); below it each wave reads its phases with
+// scalar loads (3501 points, K = 50, S = 64: 22.6 us instead of 25.0 us).
+constexpr int kWinStageK = 128;
+
+struct WinSmem {
+    int4 rg[kWinChunk];
+    float4 pk[kWinChunk];
+    int2 rg2[kWinChunk];
+    float pkr[kWinChunk];
+    int off[kWinChunk];
+    int wsum[kWaves];
+    float4 pd[kWinPeaks];
+    float sig[kWaves][kTile];
+    float rres[kTile];
+    double red[kWaves];
+};
+
+// Shared memory of a windowed tile of either kind.
+union WinTileSmem {
+    FusedSmem f;
+    WinSmem w;
+};
+
+template <bool ASYM>
+__device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
+                         float *f_out, WinSmem &sm) {
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int i0 = t * kTile;
+    const int K = P.K;
+    const int4 *rng = st.rng + ((size_t)s * P.ntiles + t) * K;
+    const int2 *rng2 = ASYM ? st.rng2 + ((size_t)s * P.ntiles + t) * K : nullptr;
+    const float4 *pkv = st.pk + (size_t)s * K;
+    const float *pkrv = ASYM ? st.pkr + (size_t)s * K : nullptr;
+    const float *ptt = P.pt + (size_t)t * P.T;
+    const int *wlo = st.lo + (size_t)s * P.T;
+    const int *whi = st.hi + (size_t)s * P.T;
+    SegPeaks sp;
+    sp.pt = as_const(ptt);
+    sp.inten = as_const(P.inten);
+    sp.wlo = as_const(wlo);
+    sp.whi = as_const(whi);
+
+    float u[kPPL];
+    int idx[kPPL];
+    float sig[kPPL];
+#pragma unroll
+    for (int p = 0; p < kPPL; ++p) {
+        idx[p] = i0 + p * kWave + lane;
+        u[p] = P.u[idx[p]];
+        sig[p] = 0.f;
+    }
+
+    for (int c0 = 0; c0 < K; c0 += kWinChunk) {
+        const int nk = min(kWinChunk, K - c0);
+        // ranges, constants and peak counts of this chunk's phases
+        int cnt = 0, ja = 0;
+        if (tid < nk) {
+            const int4 r = rng[c0 + tid];
+            sm.rg[tid] = r;
+            sm.pk[tid] = pkv[c0 + tid];
+            if (ASYM) {
+                sm.rg2[tid] = rng2[c0 + tid];
+                sm.pkr[tid] = pkrv[c0 + tid];
+            }
+            ja = r.x;
+            cnt = r.w - r.x;
+        }
+        // exclusive prefix of the counts over the block
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int v = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += v;
+        }
+        if (lane == kWave - 1) sm.wsum[wv] = incl;
+        __syncthreads();
+        int before = 0;
+        for (int w = 0; w < wv; ++w) before += sm.wsum[w];
+        const int excl = before + incl - cnt;
+        if (tid < nk) sm.off[tid] = excl;
+        for (int q = 0; q < cnt && excl + q < kWinPeaks; ++q) {
+            const int j = ja + q;
+            sm.pd[excl + q] = make_float4(ptt[j], P.inten[j], __int_as_float(wlo[j]),
+                                          __int_as_float(whi[j]));
+        }
+        __syncthreads();
+
+        for (int kl = wv; kl < nk; kl += kWaves) {
+            const int4 r = sm.rg[kl];
+            const int ja_k = __builtin_amdgcn_readfirstlane(r.x);
+            const int ga = __builtin_amdgcn_readfirstlane(r.y);
+            const int gb = __builtin_amdgcn_readfirstlane(r.z);
+            const int jb = __builtin_amdgcn_readfirstlane(r.w);
+            if (ja_k >= jb) continue;
+            const float4 c = sm.pk[kl];
+            const float iw2 = c.x, aG = c.y, aL = c.z, mu = c.w;
+            const float iw2r = ASYM ? sm.pkr[kl] : iw2;
+            int jr = gb, jl = gb;
+            if (ASYM) {
+                const int2 r2 = sm.rg2[kl];
+                jr = __builtin_amdgcn_readfirstlane(r2.x);
+                jl = __builtin_amdgcn_readfirstlane(r2.y);
+            }
+            float uq[kPPL], uqr[kPPL], accL[kPPL], accG[kPPL];
+#pragma unroll
+            for (int p = 0; p < kPPL; ++p) {
+                uq[p] = (u[p] - mu) * iw2;
+                uqr[p] = ASYM ? (u[p] - mu) * iw2r : uq[p];
+                accL[p] = 0.f;
+                accG[p] = 0.f;
+            }
+            auto run = [&](const auto &pks) {
+                if (ASYM) {
+                    fwd_segment<true, false, kAbove>(pks, ja_k, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
+                    fwd_segment<true, true, kAbove>(pks, ga, jr, idx, uq, uqr, iw2, iw2r, accL, accG);
+                    fwd_segment<true, true, kBoth>(pks, jr, jl, idx, uq, uqr, iw2, iw2r, accL, accG);
+                    fwd_segment<true, true, kBelow>(pks, jl, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
+                    fwd_segment<true, false, kBelow>(pks, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
+                } else {
+                    fwd_segment<true, false, kBelow>(pks, ja_k, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
+                    fwd_segment<true, true, kBelow>(pks, ga, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
+                    fwd_segment<true, false, kBelow>(pks, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
+                }
+            };
+            const int base = __builtin_amdgcn_readfirstlane(sm.off[kl]);
+            if (base + (jb - ja_k) <= kWinPeaks) run(LdsPeaks{sm.pd, base - ja_k});
+            else run(sp);
+#pragma unroll
+            for (int p = 0; p < kPPL; ++p)
+                sig[p] = fmaf(aL, accL[p], fmaf(aG, accG[p], sig[p]));
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int p = 0; p < kPPL; ++p) sm.sig[wv][p * kWave + lane] = sig[p];
+    __syncthreads();
+    tile_points(P, st, t, s, f_out, sm.sig, sm.rres, sm.red);
+}
+
 // ---- peak-major adjoint (windowed mode) -----------------------------------
 //
 // One block of kWaves waves per (sample s, phase k); wave w takes peaks
@@ -645,6 +834,55 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
 // rounded to FP32 (its sign picks the side of an asymmetric peak).  Six
 // sums (twelve: six per side) accumulate per lane over the wave's peaks,
 // are reduced over the wave, then over the waves in fixed order.
+template <bool ASYM>
+__device__ __forceinline__ void adj_point(bool valid, float R, double d,
+                                          float iw2, float iw2r,
+                                          float (&acc)[ASYM ? 12 : 6]) {
+    const bool up = ASYM && d >= 0.0;
+    const float q2 = (float)d * (up ? iw2r : iw2);
+    const float tt = fmaf(q2, q2, 1.0f);
+    const float l = rcp_f32(tt);
+    const float Rl = R * l;
+    const float Rll = Rl * l;
+    float Re = 0.f, Req = 0.f;
+    const bool gauss = __builtin_expect(__any(valid && tt < 81.0f), 0);
+    if (gauss) {
+        Re = R * exp2_f32(1.0f - tt);
+        Req = Re * q2;
+    }
+    if (!ASYM) {
+        acc[3] += Rl;
+        acc[5] += Rll;
+        acc[4] = fmaf(Rll, q2, acc[4]);
+        if (gauss) {
+            acc[0] += Re;
+            acc[1] += Req;
+            acc[2] = fmaf(Req, q2, acc[2]);
+        }
+    } else {
+        const float Rllq = Rll * q2, Reqq = Req * q2;
+        const float fu = up ? 1.f : 0.f, fd = 1.f - fu;
+        acc[3] = fmaf(fd, Rl, acc[3]);
+        acc[9] = fmaf(fu, Rl, acc[9]);
+        acc[5] = fmaf(fd, Rll, acc[5]);
+        acc[11] = fmaf(fu, Rll, acc[11]);
+        acc[4] = fmaf(fd, Rllq, acc[4]);
+        acc[10] = fmaf(fu, Rllq, acc[10]);
+        if (gauss) {
+            acc[0] = fmaf(fd, Re, acc[0]);
+            acc[6] = fmaf(fu, Re, acc[6]);
+            acc[1] = fmaf(fd, Req, acc[1]);
+            acc[7] = fmaf(fu, Req, acc[7]);
+            acc[2] = fmaf(fd, Reqq, acc[2]);
+            acc[8] = fmaf(fu, Reqq, acc[8]);
+        }
+    }
+}
+
+// Peaks a wave handles together: their scalar data and grid loads are issued
+// back to back, so one memory latency covers all of them.
+constexpr int kAdjPeaks = 4;
+
 template <bool ASYM>
 __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
                                      int s, int k, double (*red)[12]) {
@@ -665,55 +903,39 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
     float acc[NS];
 #pragma unroll
     for (int c = 0; c < NS; ++c) acc[c] = 0.f;
-    for (int j = a + wv; j < b; j += kWaves) {
-        const int lo = wlo[j], hi = whi[j];
-        const float I = inten[j];
-        const double rho = pos[j] + mu;
-        for (int c = lo; c < hi; c += kWave) {
-            const int i = c + lane;
-            const bool valid = i < hi;
-            const int ii = valid ? i : lo;
-            const float R = valid ? rres[ii] * I : 0.f;
-            const double d = P.x[ii] - rho;
-            const bool up = ASYM && d >= 0.0;
-            const float q2 = (float)d * (up ? iw2r : iw2);
-            const float tt = fmaf(q2, q2, 1.0f);
-            const float l = rcp_f32(tt);
-            const float Rl = R * l;
-            const float Rll = Rl * l;
-            float Re = 0.f, Req = 0.f;
-            const bool gauss = __builtin_expect(__any(valid && tt < 81.0f), 0);
-            if (gauss) {
-                Re = R * exp2_f32(1.0f - tt);
-                Req = Re * q2;
+    // wave wv takes peaks a + wv + kWaves * (kAdjPeaks * g + q), q < kAdjPeaks
+    for (int j0 = a + wv; j0 < b; j0 += kWaves * kAdjPeaks) {
+        int lo[kAdjPeaks], len[kAdjPeaks];
+        float I[kAdjPeaks];
+        double rho[kAdjPeaks];
+        int span = 0;
+#pragma unroll
+        for (int q = 0; q < kAdjPeaks; ++q) {
+            const int j = j0 + kWaves * q;
+            const bool ok = j < b;
+            const int jj = ok ? j : j0;
+            lo[q] = wlo[jj];
+            len[q] = ok ? whi[jj] - lo[q] : 0;
+            I[q] = inten[jj];
+            rho[q] = pos[jj] + mu;
+            span = max(span, len[q]);
+        }
+        for (int c = 0; c < span; c += kWave) {
+            float R[kAdjPeaks];
+            double d[kAdjPeaks];
+            bool valid[kAdjPeaks];
+#pragma unroll
+            for (int q = 0; q < kAdjPeaks; ++q) {
+                valid[q] = c + lane < len[q];
+                // lanes outside the window read point 0 (lo can be N for an
+                // empty window at the end of the grid)
+                const int ii = valid[q] ? lo[q] + c + lane : 0;
+                R[q] = valid[q] ? rres[ii] * I[q] : 0.f;
+                d[q] = P.x[ii] - rho[q];
             }
-            if (!ASYM) {
-                acc[3] += Rl;
-                acc[5] += Rll;
-                acc[4] = fmaf(Rll, q2, acc[4]);
-                if (gauss) {
-                    acc[0] += Re;
-                    acc[1] += Req;
-                    acc[2] = fmaf(Req, q2, acc[2]);
-                }
-            } else {
-                const float Rllq = Rll * q2, Reqq = Req * q2;
-                const float fu = up ? 1.f : 0.f, fd = 1.f - fu;
-                acc[3] = fmaf(fd, Rl, acc[3]);
-                acc[9] = fmaf(fu, Rl, acc[9]);
-                acc[5] = fmaf(fd, Rll, acc[5]);
-                acc[11] = fmaf(fu, Rll, acc[11]);
-                acc[4] = fmaf(fd, Rllq, acc[4]);
-                acc[10] = fmaf(fu, Rllq, acc[10]);
-                if (gauss) {
-                    acc[0] = fmaf(fd, Re, acc[0]);
-                    acc[6] = fmaf(fu, Re, acc[6]);
-                    acc[1] = fmaf(fd, Req, acc[1]);
-                    acc[7] = fmaf(fu, Req, acc[7]);
-                    acc[2] = fmaf(fd, Reqq, acc[2]);
-                    acc[8] = fmaf(fu, Reqq, acc[8]);
-                }
-            }
+#pragma unroll
+            for (int q = 0; q < kAdjPeaks; ++q)
+                adj_point<ASYM>(valid[q], R[q], d[q], iw2, iw2r, acc);
         }
     }
 #pragma unroll

@@ -83,6 +83,15 @@ __global__ __launch_bounds__(kBlock) void k_fused(ProbDev P, StepDev st,
     fused_tile<WIN, GRAD, ASYM>(P, st, blockIdx.x, blockIdx.y, f_out, sm);
 }
 
+// a3 + a4 (windowed): forward tile with LDS-staged peak lists; grid
+// (ntiles, S), kBlock threads.
+template <bool ASYM>
+__global__ __launch_bounds__(kBlock) void k_win(ProbDev P, StepDev st,
+                                                float *f_out) {
+    __shared__ WinSmem sm;
+    win_tile<ASYM>(P, st, blockIdx.x, blockIdx.y, f_out, sm);
+}
+
 // a6 (windowed): peak-major adjoint, one block per (sample, phase);
 // grid (K, S), kBlock threads.
 template <bool ASYM>
@@ -179,7 +188,8 @@ static void launch_fused_t(const ProbDev &P, const StepDev &st, bool grad,
     if (P.cutoff > 0.0) {
         StepDev sf = st;
         if (!grad) sf.rres = nullptr;
-        k_fused<true, false, ASYM><<<g, kBlock, 0, stream>>>(P, sf, f_out);
+        if (P.K >= kWinStageK) k_win<ASYM><<<g, kBlock, 0, stream>>>(P, sf, f_out);
+        else k_fused<true, false, ASYM><<<g, kBlock, 0, stream>>>(P, sf, f_out);
         if (grad) {
             dim3 ga(P.K, st.S);
             k_adjoint_win<ASYM><<<ga, kBlock, 0, stream>>>(P, st);

@@ -45,6 +45,8 @@ PROFILE_CASES = [
     ("paper50", 503, {}, 8, 8.0),
     ("paper50", 504, dict(N=1000), 4, 3.0),          # ragged last tile
     ("paper50", 505, dict(N=77, K=5, M=3), 3, 2.0),  # one partial tile
+    ("stress200", 506, dict(K=300, M=20, N=3001), 2, 8.0),  # staged in LDS
+    ("stress200", 507, dict(K=260, M=100, N=600), 2, 8.0),  # staging overflow
 ]
 
 
@@ -90,6 +92,8 @@ ELBO_CASES = [
     ("paper50", 603, {}, 64, 8.0),
     ("paper50", 604, dict(N=1000), 5, 0.0),
     ("paper50", 605, dict(N=1000), 5, 3.0),
+    ("stress200", 606, dict(K=300, M=20, N=3001), 3, 8.0),
+    ("stress200", 607, dict(K=260, M=100, N=600), 3, 8.0),
 ]
 
 

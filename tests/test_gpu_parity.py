@@ -34,6 +34,10 @@ PROFILE_CASES = [
     ("paper50", 104, dict(N=1000), 4, 0.0),        # ragged last tile
     ("paper50", 105, dict(N=77, K=5, M=3), 3, 2.0),  # one partial tile
     ("stress200", 106, dict(K=40), 2, 8.0),
+    # many phases: the windowed forward stages peak lists in LDS, two chunks
+    ("stress200", 107, dict(K=300, M=20, N=3001), 2, 8.0),
+    # more peaks reaching a tile than the staging holds (scalar overflow)
+    ("stress200", 108, dict(K=260, M=100, N=600), 2, 8.0),
 ]
 
 
@@ -75,6 +79,8 @@ ELBO_CASES = [
     ("paper50", 202, {}, 64, 0.0),
     ("paper50", 203, {}, 64, 8.0),
     ("paper50", 204, dict(N=1000), 5, 0.0),
+    ("stress200", 205, dict(K=300, M=20, N=3001), 4, 8.0),
+    ("stress200", 206, dict(K=260, M=100, N=600), 3, 8.0),
 ]
 
 
