@@ -160,6 +160,8 @@ hipError_t upload_problem(const xrdvi_problem_desc &d, double lambda,
     P.N = N; P.K = K; P.T = T; P.ntiles = num_tiles(N);
     P.D = latent_types(d);
     P.cutoff = d.cutoff;
+    P.x0 = d.x[0];
+    P.inv_dx = N > 1 ? (double)(N - 1) / (d.x[N - 1] - d.x[0]) : 0.0;
     P.lambda = lambda;
     P.mu_sd = d.prior.mu_sd;
     P.w_shape = d.prior.w_shape;

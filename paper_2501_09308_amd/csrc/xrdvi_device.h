@@ -60,6 +60,8 @@ struct ProbDev {
     // shape ln(rate) - lgamma(shape), -ln(a_sd sqrt(2 pi))
     double c_h, c_mu, c_w, c_a;
     const double *x, *y, *bg, *lgy;   // [N]; lgy = ln y!
+    double x0, inv_dx;                // x[0] and (N - 1) / (x[N-1] - x[0])
+                                      // (0 for N = 1): grid-search guesses
     const float *u;                   // [ntiles * kTile] x_i - xref_tile
     const int *off;                   // [K + 1]
     const int *phase;                 // [T] phase of each peak
@@ -177,23 +179,55 @@ __device__ __forceinline__ float asym_iw2(double w, double alpha) {
 
 // ---- window plan ---------------------------------------------------------
 
-// First i with x[i] >= v.
-__device__ inline int lower_bound_x(const double *x, int n, double v) {
+// Grid searches.  The grid is ascending and usually close to uniform, so
+// the search starts at the index a uniform grid would give, walks a few
+// points checking the true values, and only falls back to bisection of the
+// remaining bracket when the walk does not settle: the result is the exact
+// bound for any ascending grid.
+
+// Index guess for value v on a grid starting at x0 with inv_dx points per
+// unit (clamped to [0, n]; NaN gives 0).
+__host__ __device__ inline int grid_guess(double x0, double inv_dx, int n,
+                                          double v) {
+    const double g = (v - x0) * inv_dx;
+    if (!(g > 0.0)) return 0;
+    if (!(g < (double)n)) return n;
+    return (int)g;
+}
+
+// First i with x[i] >= v (STRICT = false) or x[i] > v (STRICT = true).
+template <bool STRICT>
+__host__ __device__ inline int grid_bound(const double *x, int n, double x0,
+                                          double inv_dx, double v) {
+    auto before = [&](int i) { return STRICT ? x[i] <= v : x[i] < v; };
+    int i = grid_guess(x0, inv_dx, n, v);
+    // the bound lies in [lo, hi]: i is a candidate, move towards it
     int lo = 0, hi = n;
+    for (int step = 0; step < 4; ++step) {
+        if (i > 0 && !before(i - 1)) {          // bound is at or left of i - 1
+            hi = i - 1;
+            --i;
+        } else if (i < n && before(i)) {        // bound is right of i
+            lo = i + 1;
+            ++i;
+        } else {
+            return i;                           // x[i-1] before v, x[i] not
+        }
+    }
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (x[mid] < v) lo = mid + 1; else hi = mid;
+        if (before(mid)) lo = mid + 1; else hi = mid;
     }
     return lo;
 }
-// First i with x[i] > v.
-__device__ inline int upper_bound_x(const double *x, int n, double v) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (x[mid] <= v) lo = mid + 1; else hi = mid;
-    }
-    return lo;
+
+__device__ inline int lower_bound_x(const double *x, int n, double x0,
+                                    double inv_dx, double v) {
+    return grid_bound<false>(x, n, x0, inv_dx, v);
+}
+__device__ inline int upper_bound_x(const double *x, int n, double x0,
+                                    double inv_dx, double v) {
+    return grid_bound<true>(x, n, x0, inv_dx, v);
 }
 
 // Grid range [lo, hi) with rho - c w <= x_i <= rho + c w (rho + (c w) alpha
@@ -207,8 +241,8 @@ __device__ inline int2 window_of(const ProbDev &P, double p, double mu,
     const double hw = P.cutoff * w;
     const double a = rho - hw;
     const double b = rho + (P.D == 5 ? hw * alpha : hw);
-    const int lo = lower_bound_x(P.x, P.N, a);
-    int hi = upper_bound_x(P.x, P.N, b);
+    const int lo = lower_bound_x(P.x, P.N, P.x0, P.inv_dx, a);
+    int hi = upper_bound_x(P.x, P.N, P.x0, P.inv_dx, b);
     if (hi < lo) hi = lo;
     return make_int2(lo, hi);
 }

@@ -1,0 +1,54 @@
+// Host check of the guessed-then-walked grid search against std::lower_bound
+// and std::upper_bound on uniform, jittered and strongly non-uniform grids.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <limits>
+#include <random>
+#include <vector>
+
+#include "xrdvi_device.h"
+
+int main() {
+    std::mt19937_64 rng(7);
+    std::uniform_real_distribution<double> U(0.0, 1.0);
+    long bad = 0, checks = 0;
+    for (int g = 0; g < 300; ++g) {
+        const int n = 1 + (int)(U(rng) * 3000);
+        std::vector<double> x(n);
+        const int kind = g % 3;
+        double v = 10.0;
+        for (int i = 0; i < n; ++i) {
+            if (kind == 0) x[i] = 10.0 + i * 0.02;                        // uniform
+            else if (kind == 1) x[i] = 10.0 + i * 0.02 + 0.004 * U(rng);  // jitter
+            else { v += 1e-4 + std::pow(U(rng), 4.0); x[i] = v; }         // ragged
+        }
+        for (int i = 1; i < n; ++i)
+            if (!(x[i] > x[i - 1])) x[i] = std::nextafter(x[i - 1], 1e300);
+        const double x0 = x[0];
+        const double inv = n > 1 ? (n - 1) / (x[n - 1] - x[0]) : 0.0;
+        for (int q = 0; q < 400; ++q) {
+            double val;
+            const double r = U(rng);
+            if (r < 0.3) val = x[(size_t)(U(rng) * n) % n];               // on a point
+            else if (r < 0.95) val = x[0] - 1.0 + (x[n - 1] - x[0] + 2.0) * U(rng);
+            else if (r < 0.97) val = std::numeric_limits<double>::infinity();
+            else if (r < 0.99) val = -std::numeric_limits<double>::infinity();
+            else val = std::nan("");
+            const int lo = xrdvi::grid_bound<false>(x.data(), n, x0, inv, val);
+            const int hi = xrdvi::grid_bound<true>(x.data(), n, x0, inv, val);
+            int rlo = (int)(std::lower_bound(x.begin(), x.end(), val) - x.begin());
+            int rhi = (int)(std::upper_bound(x.begin(), x.end(), val) - x.begin());
+            // NaN compares false with everything: both bounds are 0 (the
+            // window plan then gives an empty window)
+            if (std::isnan(val)) rlo = rhi = 0;
+            checks += 2;
+            if (lo != rlo || hi != rhi) {
+                if (bad < 5) std::printf("n=%d kind=%d v=%.17g: %d %d vs %d %d\n", n, kind, val, lo, hi, rlo, rhi);
+                ++bad;
+            }
+        }
+    }
+    std::printf("%ld checks, %ld mismatches\n", checks, bad);
+    return bad != 0;
+}

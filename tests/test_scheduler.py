@@ -266,3 +266,4 @@ def test_resident_budget_admits_one_oversized_job(lib):
     assert all(r[0] == OK for r in res.values())
     assert f.stats()[0] == 1
     f.close()
+
