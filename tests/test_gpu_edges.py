@@ -1,0 +1,99 @@
+"""Edge cases of the HIP path against the FP64 oracle: one phase with one
+peak, ragged candidate lists with empty phases and zero-intensity peaks,
+peaks outside the grid, a one-point grid, the largest sample count, and a
+window wider than the grid (which must equal the dense sum)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_09308_amd import workloads as W
+from paper_2501_09308_amd import xrdvi as X
+
+from gpu_common import context, dev, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+ELBO_RTOL = 1e-6
+GRAD_RTOL = 1e-4
+
+
+def _ragged(seed, N=1500, K=9, c=0.0):
+    """Candidates with 0..12 peaks per phase, some of intensity zero and
+    some outside the grid; counts from two generating phases."""
+    rng = np.random.default_rng(seed)
+    x = 20.0 + 0.02 * np.arange(N)
+    M = rng.integers(0, 13, K)
+    M[2] = 0
+    M[5] = 0
+    off = np.concatenate([[0], np.cumsum(M)]).astype(np.int32)
+    pos = rng.uniform(x[0] - 3.0, x[-1] + 3.0, off[-1])
+    inten = rng.uniform(0, 1, off[-1]) ** 3
+    inten[::7] = 0.0
+    phi = W.random_phi(K, 1, seed)[0]
+    phi[0] = 0.0
+    phi[0, [0, 4]] = 8e3
+    prob = W.Problem(x=x, bg=np.full(N, 50.0), peak_off=off, peak_pos=pos,
+                     peak_int=inten, cutoff=c, true_idx=np.array([0, 4]),
+                     phi_true=phi)
+    f = oracle.profile(x, prob.bg, off, pos, inten, 0.0, phi)[0]
+    return prob, W.poisson_counts(f, seed + 1)
+
+
+def _check(prob, y, S, seed, c):
+    ctx = context()
+    P = X.Problem.from_workload(ctx, prob, y, cutoff=c)
+    loc, ls = W.random_params(prob.K, seed, (y - prob.bg).max())
+    eps = W.eps_draw(S, prob.K, seed)
+    tape = X.Tape(ctx, P, S)
+    e, ll = X.xrdvi_elbo_fwd(ctx, P, tape, dev(loc), dev(ls), eps=dev(eps))
+    gl, gs = X.xrdvi_elbo_bwd(ctx, tape)
+    re, rll, rgl, rgs = oracle.elbo(prob, y, loc, ls, eps, c=c)
+    assert abs(e.item() - re) <= ELBO_RTOL * abs(re)
+    np.testing.assert_allclose(ll.cpu().numpy(), rll, rtol=ELBO_RTOL)
+    g = np.concatenate([gl.cpu().numpy().ravel(), gs.cpu().numpy().ravel()])
+    assert rel_l2(g, np.concatenate([rgl.ravel(), rgs.ravel()])) <= GRAD_RTOL
+    return gl.cpu().numpy(), gs.cpu().numpy(), rgl, rgs
+
+
+@pytest.mark.parametrize("c", [0.0, 6.0])
+def test_ragged_candidates_with_empty_phases(c):
+    prob, y = _ragged(31, c=c)
+    gl, gs, rgl, rgs = _check(prob, y, 5, 32, c)
+    # a phase without peaks feels only its prior, Jacobian and entropy
+    for k in (2, 5):
+        np.testing.assert_allclose(gl[:, k], rgl[:, k], rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("c", [0.0, 4.0])
+def test_one_phase_one_peak(c):
+    x = 30.0 + 0.01 * np.arange(700)
+    prob = W.Problem(x=x, bg=np.full(x.size, 20.0), peak_off=np.array([0, 1], np.int32),
+                     peak_pos=np.array([33.3]), peak_int=np.array([1.0]), cutoff=c,
+                     true_idx=np.array([0]),
+                     phi_true=np.array([[5e3], [0.01], [0.08], [0.4]]))
+    f = oracle.profile(x, prob.bg, prob.peak_off, prob.peak_pos, prob.peak_int, 0.0,
+                       prob.phi_true)[0]
+    _check(prob, W.poisson_counts(f, 3), 7, 4, c)
+
+
+def test_one_point_grid():
+    prob, y = _ragged(41, N=1)
+    _check(prob, np.maximum(y, 60.0), 3, 42, 0.0)
+
+
+def test_largest_sample_count():
+    prob = W.make_problem("tiny", seed=51, N=400, K=3, M=5)
+    f = oracle.profile(prob.x, prob.bg, prob.peak_off, prob.peak_pos, prob.peak_int,
+                       0.0, prob.phi_true)[0]
+    _check(prob, W.poisson_counts(f, 52), 1024, 53, 0.0)
+
+
+def test_window_wider_than_the_grid_equals_dense():
+    prob, y = _ragged(61)
+    ctx = context()
+    phi = W.random_phi(prob.K, 4, 62)
+    f0 = X.xrdvi_profile(ctx, X.Problem.from_workload(ctx, prob, y, cutoff=0.0),
+                         dev(phi)).cpu().numpy()
+    fw = X.xrdvi_profile(ctx, X.Problem.from_workload(ctx, prob, y, cutoff=1e6),
+                         dev(phi)).cpu().numpy()
+    np.testing.assert_allclose(fw, f0, rtol=2e-6)
