@@ -181,3 +181,28 @@ def test_slot_reuse_by_analyses_of_other_shapes():
         ref = X.xrdvi_plain_run(ctx, p, y, S, 6, 50 + i)
         for k in ("loc", "logscale", "trace"):
             np.testing.assert_allclose(out[k], ref[k], rtol=1e-12, atol=1e-12)
+
+
+def test_many_phase_windowed_analyses_in_the_server():
+    """Windowed analyses with K >= 128 (their batched forward stages peak
+    lists in LDS), symmetric and asymmetric, served beside small ones, must
+    match their one-at-a-time runs."""
+    ctx = context()
+    big, yb = small_case(900, N=3000, K=160, M=25, cutoff=8.0)
+    small, ys = small_case(901, N=1500, K=8, M=12, cutoff=8.0)
+    S, steps = 4, 6
+    ref = {
+        "sym": X.xrdvi_plain_run(ctx, big, yb, S, steps, 11),
+        "asym": X.xrdvi_plain_run(ctx, big, yb, S, steps, 12, asymmetric=True),
+    }
+    srv = X.Server(max_slots=6, steps_per_launch=2, arena_bytes=1 << 29)
+    others = [srv.submit(small, ys, 3, 5, 40 + i) for i in range(3)]
+    t_sym = srv.submit(big, yb, S, steps, 11)
+    t_asym = srv.submit(big, yb, S, steps, 12, asymmetric=True)
+    res = wait_all(srv, others + [t_sym, t_asym])
+    srv.close()
+    assert all(r[0] == X.XRDVI_OK for r in res.values())
+    for name, t in (("sym", t_sym), ("asym", t_asym)):
+        for k in ("loc", "logscale", "trace"):
+            np.testing.assert_allclose(res[t][2][k], ref[name][k], rtol=1e-12,
+                                       atol=1e-12)
