@@ -682,6 +682,15 @@ void oracle_eps_philox(int S, int K, uint64_t seed, uint64_t step,
     oracle_eps_philox_n(S, 4 * K, seed, step, eps);
 }
 
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

@@ -60,6 +60,7 @@ def load():
     lib.oracle_readout.argtypes = [C.c_int, _I, _D, _D, _D, C.c_double,
                                    _D, _D, _D, _I]
     lib.oracle_num_threads.restype = C.c_int
+    lib.oracle_set_threads.argtypes = [C.c_int]
     lib.oracle_profile_asym.argtypes = lib.oracle_profile.argtypes
     lib.oracle_windows_asym.argtypes = lib.oracle_windows.argtypes
     lib.oracle_elbo_asym.argtypes = ([C.c_int, C.c_int, _D, _D, _D, _I, _D, _D]
@@ -259,3 +260,8 @@ def readout(peak_off, peak_int, m_h, logscale_h, threshold=0.01):
 
 def num_threads():
     return load().oracle_num_threads()
+
+
+def set_threads(n):
+    """OpenMP threads of later oracle calls."""
+    load().oracle_set_threads(int(n))
