@@ -30,6 +30,8 @@
  *  - an optional window: peak m of phase k contributes at x_i only when
  *    rho - c w <= x_i <= rho + c w (c = 0 means every point, the paper's
  *    dense sum).
+ *  - optional width law: FWHM w_k sec(rho_mk / 2), with rho in degrees
+ *    2-theta (Appendix A.2 defines sec; the formula using it is lost).
  *
  * Parity status: the peak shape, window rule, likelihood, priors, ELBO
  * assembly and gradient are pinned by the CPU tests (closed-form areas and
@@ -561,6 +563,247 @@ int oracle_elbo_asym(int N, int K, const double *x, const double *y,
             for (int s = 0; s < S; ++s) {
                 gm += gz[(size_t)s * D + j];
                 go += gz[(size_t)s * D + j] * eps[(size_t)s * D + j] * sd;
+            }
+            grad_loc[j] = gm / (double)S;
+            grad_logscale[j] = go / (double)S + 1.0;
+        }
+    }
+    free(phi); free(lpj); free(ll); free(gz); free(f);
+    return 0;
+}
+
+/* ---- width growing with the Bragg angle (Appendix A.2, sec(x)) --------- */
+/*
+ * Reading of the lost width law that uses sec(x) = 1/cos(x): the full width
+ * at half maximum of peak m of phase k follows the Scherrer-type law
+ *   W_mk = w_k sec(theta_mk),   theta_mk = rho_mk / 2  (rho in deg 2-theta),
+ * taken as w_k / |cos(rho_mk pi / 360)|, which stays positive for a shifted
+ * centre past 180 deg.  The shape is the pseudo-Voigt (or its asymmetric
+ * form) with W_mk in place of w_k, so every peak keeps unit area, and the
+ * window of a peak spans rho - c W .. rho + (c W) alpha.  w_k is the width
+ * at 2-theta -> 0.  D = 4 (h, mu, w, r) or 5 (with alpha).
+ */
+static double sec_width(double rho, double w)
+{
+    return w / fabs(cos(rho * (M_PI / 360.0)));
+}
+
+/* dW/drho = W tau with tau = tan(theta) pi / 360 (either sign of cos). */
+static double sec_tau(double rho)
+{
+    return tan(rho * (M_PI / 360.0)) * (M_PI / 360.0);
+}
+
+static int in_window_sec(double x, double rho, double W, double alpha,
+                         int D, double c)
+{
+    if (c == 0.0) return 1;
+    const double hw = c * W;
+    const double lo = rho - hw;
+    const double hi = rho + (D == 5 ? hw * alpha : hw);
+    return (lo <= x) && (x <= hi);
+}
+
+/* One peak of unit area at offset d = x - rho with FWHM W. */
+static double shape_sec(double d, double W, double r, double alpha, int D)
+{
+    if (D == 5) return voigt_asym(d, W, r, alpha);
+    return (1.0 - r) * gauss_fwhm(d, W) + r * lorentz_fwhm(d, W);
+}
+
+/* f[s][i] with phi[s][D][K]. */
+int oracle_profile_sec(int N, int K, const double *x, const double *B,
+                       const int *peak_off, const double *p, const double *I,
+                       double c, int D, int S, const double *phi, double *f)
+{
+    if (N < 1 || K < 1 || S < 1 || (D != 4 && D != 5)) return -1;
+    #pragma omp parallel for schedule(dynamic)
+    for (int s = 0; s < S; ++s) {
+        const double *h = phi + (size_t)s * D * K;
+        const double *mu = h + K, *w = h + 2 * K, *r = h + 3 * K;
+        const double *al = D == 5 ? h + 4 * K : NULL;
+        double *fs = f + (size_t)s * N;
+        for (int i = 0; i < N; ++i) fs[i] = B[i];
+        for (int k = 0; k < K; ++k) {
+            const double a = al ? al[k] : 1.0;
+            for (int m = peak_off[k]; m < peak_off[k + 1]; ++m) {
+                const double rho = p[m] + mu[k];
+                const double W = sec_width(rho, w[k]);
+                for (int i = 0; i < N; ++i) {
+                    if (!in_window_sec(x[i], rho, W, a, D, c)) continue;
+                    fs[i] += h[k] * I[m] * shape_sec(x[i] - rho, W, r[k], a, D);
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+int oracle_windows_sec(int N, int K, const double *x, const int *peak_off,
+                       const double *p, double c, int D, int S,
+                       const double *phi, int *lo, int *hi)
+{
+    if (D != 4 && D != 5) return -1;
+    const int T = peak_off[K];
+    for (int s = 0; s < S; ++s) {
+        const double *mu = phi + (size_t)s * D * K + K;
+        const double *w = mu + K;
+        const double *al = D == 5 ? mu + 3 * K : NULL;
+        for (int k = 0; k < K; ++k) {
+            for (int m = peak_off[k]; m < peak_off[k + 1]; ++m) {
+                const double rho = p[m] + mu[k];
+                const double W = sec_width(rho, w[k]);
+                int first = -1, last = -1;
+                for (int i = 0; i < N; ++i) {
+                    if (in_window_sec(x[i], rho, W, al ? al[k] : 1.0, D, c)) {
+                        if (first < 0) first = i;
+                        last = i;
+                    }
+                }
+                int *l = lo + (size_t)s * T + m, *u = hi + (size_t)s * T + m;
+                if (first < 0) {
+                    int ins = 0;
+                    while (ins < N && x[ins] < rho) ++ins;
+                    *l = ins; *u = ins;
+                } else {
+                    *l = first; *u = last + 1;
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+/*
+ * ELBO and gradient of the model with the sec width law (D = 4 or 5; the
+ * same estimator and priors as oracle_elbo / oracle_elbo_asym).  The shift
+ * mu moves each peak and, through W(rho), widens or narrows it; both parts
+ * enter d/dmu.
+ */
+int oracle_elbo_sec(int N, int K, const double *x, const double *y,
+                    const double *B, const int *peak_off, const double *p,
+                    const double *I, double c, double lambda, double mu_sd,
+                    double w_shape, double w_rate, double alpha_mean,
+                    double alpha_sd, int D, int S, const double *loc,
+                    const double *logscale, const double *eps, double *elbo,
+                    double *loglik, double *grad_loc, double *grad_logscale)
+{
+    if (N < 1 || K < 1 || S < 1 || (D != 4 && D != 5)) return -1;
+    prob_t P = {N, K, x, y, B, peak_off, p, I, c, lambda, mu_sd, w_shape,
+                w_rate};
+    if (P.lambda == 0.0) {
+        const double ymax = max_signal(&P);
+        if (!(ymax > 0.0)) return -2;
+        P.lambda = 1.0 / ymax;
+    }
+    const int DK = D * K;
+    double *phi = malloc(sizeof(double) * (size_t)S * DK);
+    double *lpj = malloc(sizeof(double) * (size_t)S);
+    double *ll = malloc(sizeof(double) * (size_t)S);
+    double *gz = malloc(sizeof(double) * (size_t)S * DK);
+    double *f = malloc(sizeof(double) * (size_t)S * N);
+    if (!phi || !lpj || !ll || !gz || !f) {
+        free(phi); free(lpj); free(ll); free(gz); free(f);
+        return -3;
+    }
+    for (int s = 0; s < S; ++s) {
+        double acc = 0.0;
+        for (int k = 0; k < K; ++k) {
+            double zz[5];
+            for (int t = 0; t < D; ++t) {
+                const int j = t * K + k;
+                const double sd = exp(logscale[j]);
+                const double step = sd * eps[(size_t)s * DK + j];
+                zz[t] = loc[j] + step;
+            }
+            double h, mu, w, r, lj;
+            transform(zz[0], zz[1], zz[2], zz[3], &h, &mu, &w, &r, &lj);
+            double *ph = phi + (size_t)s * DK;
+            ph[k] = h; ph[K + k] = mu; ph[2 * K + k] = w; ph[3 * K + k] = r;
+            acc += oracle_log_prior(h, mu, w, r, P.lambda, mu_sd, w_shape,
+                                    w_rate) + lj;
+            if (D == 5) {
+                const double al = exp(zz[4]);
+                ph[4 * K + k] = al;
+                acc += log_normal_pdf(al, alpha_mean, alpha_sd) + zz[4];
+            }
+        }
+        lpj[s] = acc;
+    }
+    oracle_profile_sec(N, K, x, B, peak_off, p, I, c, D, S, phi, f);
+    oracle_loglik(N, S, y, f, ll);
+    double mean = 0.0;
+    for (int s = 0; s < S; ++s) mean += ll[s] + lpj[s];
+    mean /= (double)S;
+    double ent = 0.0;
+    for (int j = 0; j < DK; ++j) ent += logscale[j];
+    ent += 0.5 * (double)DK * (1.0 + log(2.0 * M_PI));
+    *elbo = mean + ent;
+    if (loglik) for (int s = 0; s < S; ++s) loglik[s] = ll[s];
+
+    if (grad_loc && grad_logscale) {
+        const double ln2 = log(2.0);
+        const double cG = 2.0 * sqrt(ln2 / M_PI), cL = 2.0 / M_PI;
+        #pragma omp parallel for collapse(2) schedule(dynamic)
+        for (int s = 0; s < S; ++s) {
+            for (int k = 0; k < K; ++k) {
+                const double *ph = phi + (size_t)s * DK;
+                const double h = ph[k], mu = ph[K + k], w = ph[2 * K + k],
+                             r = ph[3 * K + k];
+                const double al = D == 5 ? ph[4 * K + k] : 1.0;
+                const double Na = D == 5 ? 2.0 / (1.0 + al) : 1.0;
+                const double *fs = f + (size_t)s * N;
+                double gh = 0.0, gmu = 0.0, gw = 0.0, gr = 0.0, ga = 0.0;
+                for (int m = peak_off[k]; m < peak_off[k + 1]; ++m) {
+                    const double rho = p[m] + mu;
+                    const double W = sec_width(rho, w);
+                    const double tau = sec_tau(rho);
+                    for (int i = 0; i < N; ++i) {
+                        if (!in_window_sec(x[i], rho, W, al, D, c)) continue;
+                        const double rres = y[i] / fs[i] - 1.0;
+                        const double d = x[i] - rho;
+                        const int right = D == 5 && d >= 0.0;
+                        const double A = right ? al : 1.0;
+                        const double q = d / (A * W);
+                        /* V = Na v(q) / W, v = (1-r) cG g + r cL lam */
+                        const double g = exp(-4.0 * ln2 * q * q);
+                        const double lam = 1.0 / (1.0 + 4.0 * q * q);
+                        const double v = (1.0 - r) * cG * g + r * cL * lam;
+                        const double dv = (1.0 - r) * cG * (-8.0 * ln2 * q) * g
+                                        + r * cL * (-8.0 * q) * lam * lam;
+                        const double a = rres * I[m];
+                        /* dV/dd at fixed W, dV/dW at fixed d */
+                        const double dVdd = Na * dv / (A * W * W);
+                        const double dVdW = -Na / (W * W) * (v + q * dv);
+                        gh += a * Na * v / W;
+                        /* drho/dmu = 1, dW/dmu = W tau */
+                        gmu += a * h * (-dVdd + dVdW * W * tau);
+                        /* dW/dw = W / w */
+                        gw += a * h * dVdW * W / w;
+                        gr += a * h * Na / W * (cL * lam - cG * g);
+                        if (D == 5)
+                            ga += a * h * (-Na / (1.0 + al) * v / W
+                                           + (right ? Na / W * dv * (-q / al)
+                                                    : 0.0));
+                    }
+                }
+                double *gzz = gz + (size_t)s * DK;
+                gzz[k] = h * gh - P.lambda * h + 1.0;
+                gzz[K + k] = gmu - mu / (mu_sd * mu_sd);
+                gzz[2 * K + k] = w * gw + (w_shape - 1.0) - w_rate * w + 1.0;
+                gzz[3 * K + k] = r * (1.0 - r) * gr + 1.0 - 2.0 * r;
+                if (D == 5)
+                    gzz[4 * K + k] = al * ga
+                                   - al * (al - alpha_mean)
+                                     / (alpha_sd * alpha_sd) + 1.0;
+            }
+        }
+        for (int j = 0; j < DK; ++j) {
+            double gm = 0.0, go = 0.0;
+            const double sd = exp(logscale[j]);
+            for (int s = 0; s < S; ++s) {
+                gm += gz[(size_t)s * DK + j];
+                go += gz[(size_t)s * DK + j] * eps[(size_t)s * DK + j] * sd;
             }
             grad_loc[j] = gm / (double)S;
             grad_logscale[j] = go / (double)S + 1.0;

@@ -66,6 +66,15 @@ def load():
     lib.oracle_elbo_asym.argtypes = ([C.c_int, C.c_int, _D, _D, _D, _I, _D, _D]
                                      + [C.c_double] * 7
                                      + [C.c_int, _D, _D, _D, _D, _D, _D, _D])
+    lib.oracle_profile_sec.argtypes = [C.c_int, C.c_int, _D, _D, _I, _D, _D,
+                                       C.c_double, C.c_int, C.c_int, _D, _D]
+    lib.oracle_windows_sec.argtypes = [C.c_int, C.c_int, _D, _I, _D,
+                                       C.c_double, C.c_int, C.c_int, _D, _I,
+                                       _I]
+    lib.oracle_elbo_sec.argtypes = ([C.c_int, C.c_int, _D, _D, _D, _I, _D, _D]
+                                    + [C.c_double] * 7
+                                    + [C.c_int, C.c_int, _D, _D, _D, _D, _D,
+                                       _D, _D])
     _lib = lib
     return lib
 
@@ -265,3 +274,64 @@ def num_threads():
 def set_threads(n):
     """OpenMP threads of later oracle calls."""
     load().oracle_set_threads(int(n))
+
+
+def profile_sec(x, B, peak_off, p, I, c, phi):
+    """f[S][N] with the sec width law; phi[S][D][K], D = 4 or 5."""
+    lib = load()
+    phi = np.asarray(phi, dtype=np.float64)
+    if phi.ndim == 2:
+        phi = phi[None]
+    S, D, K = phi.shape
+    f = np.empty((S, len(x)))
+    keep = [_d(x), _d(B), _i(peak_off), _d(p), _d(I), _d(phi)]
+    rc = lib.oracle_profile_sec(len(x), K, keep[0][1], keep[1][1], keep[2][1],
+                                keep[3][1], keep[4][1], float(c), D, S,
+                                keep[5][1], f.ctypes.data_as(_D))
+    assert rc == 0, rc
+    return f
+
+
+def windows_sec(x, peak_off, p, c, phi):
+    """Window plan (lo, hi) [S][T] with the sec width law."""
+    lib = load()
+    phi = np.asarray(phi, dtype=np.float64)
+    if phi.ndim == 2:
+        phi = phi[None]
+    S, D, K = phi.shape
+    T = int(peak_off[-1])
+    lo = np.empty((S, T), dtype=np.int32)
+    hi = np.empty((S, T), dtype=np.int32)
+    keep = [_d(x), _i(peak_off), _d(p), _d(phi)]
+    rc = lib.oracle_windows_sec(len(x), K, keep[0][1], keep[1][1], keep[2][1],
+                                float(c), D, S, keep[3][1],
+                                lo.ctypes.data_as(_I), hi.ctypes.data_as(_I))
+    assert rc == 0, rc
+    return lo, hi
+
+
+def elbo_sec(prob, y, loc, logscale, eps, *, lam=0.0, mu_sd=0.03,
+             w_shape=3.0, w_rate=100.0, alpha_mean=1.0, alpha_sd=0.2,
+             grad=True, c=None):
+    """Sec width law: loc, logscale [D][K], eps [S][D][K], D = 4 or 5."""
+    lib = load()
+    eps = np.ascontiguousarray(eps, dtype=np.float64)
+    S, D, K = eps.shape
+    assert K == prob.K
+    cut = prob.cutoff if c is None else c
+    gl = np.empty((D, K)); gs = np.empty((D, K)); ll = np.empty(S)
+    out = C.c_double(0.0)
+    keep = [_d(prob.x), _d(y), _d(prob.bg), _i(prob.peak_off),
+            _d(prob.peak_pos), _d(prob.peak_int), _d(loc), _d(logscale),
+            _d(eps)]
+    rc = lib.oracle_elbo_sec(prob.N, K, keep[0][1], keep[1][1], keep[2][1],
+                             keep[3][1], keep[4][1], keep[5][1], float(cut),
+                             float(lam), float(mu_sd), float(w_shape),
+                             float(w_rate), float(alpha_mean),
+                             float(alpha_sd), D, S, keep[6][1], keep[7][1],
+                             keep[8][1], C.byref(out), ll.ctypes.data_as(_D),
+                             gl.ctypes.data_as(_D) if grad else None,
+                             gs.ctypes.data_as(_D) if grad else None)
+    if rc != 0:
+        raise ValueError(f"oracle_elbo_sec failed: {rc}")
+    return out.value, ll, (gl if grad else None), (gs if grad else None)
