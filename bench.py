@@ -33,20 +33,21 @@ SEED = 2000
 FLOPS_PER_PEAK_POINT = 36
 PEAK_FP32_TFLOPS = 157.3
 # The dominant kernel of the dense step, as rocprofv3 names it.
-DENSE_KERNEL = "void k_fused<false, true, false>"
+DENSE_KERNEL = "void k_fused<false, true, false, false>"
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def gpu_problem(X, W, ctx, prob, cutoff, asymmetric=False):
+def gpu_problem(X, W, ctx, prob, cutoff, asymmetric=False, width_law=0):
     """Problem whose counts are a Poisson draw around the HIP profile of the
     generating phases (c = 0; asymmetric: alpha = 1.3 for every phase)."""
     import torch
     flat = np.full(prob.N, 1.0)
     P0 = X.Problem(ctx, prob.x, flat, prob.bg, prob.peak_off, prob.peak_pos,
-                   prob.peak_int, 0.0, lambda_h=1.0, asymmetric=asymmetric)
+                   prob.peak_int, 0.0, lambda_h=1.0, asymmetric=asymmetric,
+                   width_law=width_law)
     phi = prob.phi_true[None]
     if asymmetric:
         phi = np.concatenate([phi, np.full((1, 1, prob.K), 1.3)], axis=1)
@@ -55,13 +56,14 @@ def gpu_problem(X, W, ctx, prob, cutoff, asymmetric=False):
     P0.close()
     y = W.poisson_counts(fstar, SEED + 1)
     return X.Problem(ctx, prob.x, y, prob.bg, prob.peak_off, prob.peak_pos,
-                     prob.peak_int, cutoff, asymmetric=asymmetric), y
+                     prob.peak_int, cutoff, asymmetric=asymmetric,
+                     width_law=width_law), y
 
 
 def run_gpu(X, W, ctx, prob, S, cutoff, steps, warmup, count_points,
-            asymmetric=False):
+            asymmetric=False, width_law=0):
     import torch
-    P, y = gpu_problem(X, W, ctx, prob, cutoff, asymmetric)
+    P, y = gpu_problem(X, W, ctx, prob, cutoff, asymmetric, width_law)
     tape = X.Tape(ctx, P, S)
     loc, logscale = W.init_params(P.K, float((y - prob.bg).max()), P.D)
     loc = torch.as_tensor(loc, device="cuda")
@@ -334,6 +336,10 @@ def main(argv=None):
     asym = run_gpu(X, W, ctx, prob, S, 0.0, a.steps, a.warmup, False,
                    asymmetric=True)
     log(f"[bench] asymmetric done: {asym['wall_s'] / a.steps * 1e3:.3f} ms/step")
+    log("[bench] sec width law, dense c=0")
+    sec = run_gpu(X, W, ctx, prob, S, 0.0, a.steps, a.warmup, False,
+                  width_law="sec")
+    log(f"[bench] sec law done: {sec['wall_s'] / a.steps * 1e3:.3f} ms/step")
 
     log("[bench] background (asymmetric least squares)")
     bg_ctx = run_background(X, W, ctx, prob)
@@ -393,6 +399,13 @@ def main(argv=None):
             "ms_per_step": asym["wall_s"] / a.steps * 1e3,
             "kernel_ms": asym["kernel_ms"],
             "latents_per_phase": 5,
+        },
+        "sec_width_dense": {
+            "value": sum(sec["points"]) / sec["wall_s"],
+            "unit": "peak-point evals/s",
+            "ms_per_step": sec["wall_s"] / a.steps * 1e3,
+            "kernel_ms": sec["kernel_ms"],
+            "width": "w sec(rho/2)",
         },
         "context_1000_steps_s": ms_step,   # 1000 steps x ms/step / 1000
         "svi_vs_hmc": hmc_ctx,

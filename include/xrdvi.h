@@ -98,6 +98,13 @@ typedef struct {
  *               the upper bound is rho + (c w) alpha for asymmetric peaks);
  *               c = 0 keeps every point (the paper's dense sum)
  *   asymmetric  0: symmetric peaks (D = 4); 1: asymmetric peaks (D = 5)
+ *   width_law   0: every peak of phase k has full width w_k (the paper's
+ *               pseudo-Voigt); 1: the width grows with the Bragg angle,
+ *               W = w_k sec(rho / 2) = w_k / |cos(rho pi / 360)| (Appendix
+ *               A.2 defines sec(x) = 1/cos(x) for the lost width formula),
+ *               w_k being the width at 2-theta -> 0; W replaces w in the
+ *               shape and in the window, rho - c W .. rho + (c W) alpha.
+ *               Requires every peak_pos inside (0, 180).
  */
 typedef struct {
     int32_t N, K;
@@ -107,6 +114,7 @@ typedef struct {
     double cutoff;
     xrdvi_prior prior;
     int32_t asymmetric;
+    int32_t width_law;
 } xrdvi_problem_desc;
 
 XRDVI_API const char *xrdvi_last_error(void);

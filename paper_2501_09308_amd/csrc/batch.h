@@ -11,15 +11,21 @@ constexpr int kMaxSlots = 512;
 
 // Kernel kinds of one batched step, each with its own work prefix.  The
 // fused tile and the peak-major adjoint have one kernel per variant
-// (windowed or dense, symmetric or asymmetric peaks), so that each kernel
-// keeps the register budget of its single-analysis counterpart.
-enum BatchKind { kSample = 0, kWindows, kPlan, kFusedWin, kFusedDense,
-                 kFusedWinAsym, kFusedDenseAsym, kAdjoint, kAdjointAsym,
+// (windowed or dense, symmetric or asymmetric peaks, constant or sec-law
+// width), so that each kernel keeps the register budget of its
+// single-analysis counterpart.
+enum BatchKind { kSample = 0, kWindows, kWindowsSec, kPlan, kPlanSec,
+                 kFusedWin, kFusedDense, kFusedWinAsym, kFusedDenseAsym,
+                 kFusedWinSec, kFusedDenseSec, kFusedWinAsymSec,
+                 kFusedDenseAsymSec,
+                 kAdjoint, kAdjointAsym, kAdjointSec, kAdjointAsymSec,
                  kElbo, kGrad, kKinds };
 
-constexpr int fused_kind(bool win, bool asym) {
-    return asym ? (win ? kFusedWinAsym : kFusedDenseAsym)
-                : (win ? kFusedWin : kFusedDense);
+constexpr int fused_kind(bool win, bool asym, bool sec) {
+    return kFusedWin + (win ? 0 : 1) + (asym ? 2 : 0) + (sec ? 4 : 0);
+}
+constexpr int adjoint_kind(bool asym, bool sec) {
+    return kAdjoint + (asym ? 1 : 0) + (sec ? 2 : 0);
 }
 
 // Fixed persistent grids (blocks) of the batched kernels.
@@ -50,19 +56,22 @@ struct SchedDev {
 
 // Work units of each kind for one analysis.
 inline void batch_units(const ProbDev &P, int S, int units[kKinds]) {
-    const bool win = P.cutoff > 0.0, asym = P.D == 5;
+    const bool win = P.cutoff > 0.0, asym = P.D == 5, sec = P.sec != 0;
     const long long nkb = (P.K + kWave - 1) / kWave;
     for (int k = 0; k < kKinds; ++k) units[k] = 0;
     units[kSample] = (int)(S * nkb);
-    units[kWindows] = win ? (int)(((long long)S * P.T + 255) / 256) : 0;
-    units[kPlan] = (int)(((long long)S * P.ntiles * P.K + 255) / 256);
-    units[fused_kind(win, asym)] = P.ntiles * S;
-    if (win) units[asym ? kAdjointAsym : kAdjoint] = P.K * S;
+    if (win || sec)
+        units[sec ? kWindowsSec : kWindows] = (int)(((long long)S * P.T + 255) / 256);
+    units[sec ? kPlanSec : kPlan] = (int)(((long long)S * P.ntiles * P.K + 255) / 256);
+    units[fused_kind(win, asym, sec)] = P.ntiles * S;
+    if (win) units[adjoint_kind(asym, sec)] = P.K * S;
     units[kElbo] = 1;
     units[kGrad] = P.K;
 }
 
+// One batched step.  sec: also launch the sec-law variants (needed only
+// while some resident analysis uses that width law).
 hipError_t launch_batch_step(const SlotDev *tab, const SchedDev *sch,
-                             hipStream_t stream);
+                             hipStream_t stream, bool sec);
 
 }  // namespace xrdvi

@@ -87,10 +87,11 @@ __global__ __launch_bounds__(256) void kb_sample(const SlotDev *tab,
     }
 }
 
+template <bool SEC>
 __global__ __launch_bounds__(256) void kb_windows(const SlotDev *tab,
                                                   const SchedDev *sch) {
     __shared__ PrefixSmem ps;
-    load_prefix(sch, kWindows, ps);
+    load_prefix(sch, SEC ? kWindowsSec : kWindows, ps);
     const int total = uniform(ps.pre[ps.n]);
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         const int i = find_slot(ps, u);
@@ -98,31 +99,33 @@ __global__ __launch_bounds__(256) void kb_windows(const SlotDev *tab,
         if (!running(d)) continue;
         const size_t g = (size_t)local_unit(ps, i, u) * 256 + threadIdx.x;
         if (g < (size_t)d.st.S * d.P.T)
-            windows_elem(d.P, d.st.phi, d.st.lo, d.st.hi, nullptr, g);
+            windows_elem<SEC>(d.P, d.st.phi, d.P.cutoff > 0.0 ? d.st.lo : nullptr,
+                              d.st.hi, nullptr, g, d.st.psec);
     }
 }
 
+template <bool SEC>
 __global__ __launch_bounds__(256) void kb_plan(const SlotDev *tab,
                                                const SchedDev *sch) {
     __shared__ PrefixSmem ps;
-    load_prefix(sch, kPlan, ps);
+    load_prefix(sch, SEC ? kPlanSec : kPlan, ps);
     const int total = uniform(ps.pre[ps.n]);
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         const int i = find_slot(ps, u);
         const SlotDev &d = slot_entry(tab, ps, i);
         if (!running(d)) continue;
         const size_t g = (size_t)local_unit(ps, i, u) * 256 + threadIdx.x;
-        if (g < (size_t)d.st.S * d.P.ntiles * d.P.K) plan_elem(d.P, d.st, d.st.phi, g);
+        if (g < (size_t)d.st.S * d.P.ntiles * d.P.K) plan_elem<SEC>(d.P, d.st, d.st.phi, g);
     }
 }
 
-template <bool WIN, bool ASYM>
+template <bool WIN, bool ASYM, bool SEC>
 __global__ __launch_bounds__(kBlock) void kb_fused(const SlotDev *tab,
                                                    const SchedDev *sch) {
-    using Smem = typename std::conditional<WIN, WinTileSmem, FusedSmem>::type;
+    using Smem = typename std::conditional<WIN, WinTileSmem<SEC>, FusedSmem>::type;
     __shared__ PrefixSmem ps;
     __shared__ Smem sm;
-    load_prefix(sch, fused_kind(WIN, ASYM), ps);
+    load_prefix(sch, fused_kind(WIN, ASYM, SEC), ps);
     const int total = uniform(ps.pre[ps.n]);
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         const int i = find_slot(ps, u);
@@ -133,21 +136,21 @@ __global__ __launch_bounds__(kBlock) void kb_fused(const SlotDev *tab,
         if (s >= d.st.S) continue;
         // windowed: forward only (the adjoint is peak-major); dense: fused
         if constexpr (WIN) {
-            if (d.P.K >= kWinStageK) win_tile<ASYM>(d.P, d.st, t, s, nullptr, sm.w);
-            else fused_tile<true, false, ASYM>(d.P, d.st, t, s, nullptr, sm.f);
+            if (d.P.K >= kWinStageK) win_tile<ASYM, SEC>(d.P, d.st, t, s, nullptr, sm.w);
+            else fused_tile<true, false, ASYM, SEC>(d.P, d.st, t, s, nullptr, sm.f);
         } else {
-            fused_tile<false, true, ASYM>(d.P, d.st, t, s, nullptr, sm);
+            fused_tile<false, true, ASYM, SEC>(d.P, d.st, t, s, nullptr, sm);
         }
         __syncthreads();
     }
 }
 
-template <bool ASYM>
+template <bool ASYM, bool SEC>
 __global__ __launch_bounds__(kBlock) void kb_adjoint(const SlotDev *tab,
                                                      const SchedDev *sch) {
     __shared__ PrefixSmem ps;
     __shared__ double red[kWaves][12];
-    load_prefix(sch, ASYM ? kAdjointAsym : kAdjoint, ps);
+    load_prefix(sch, adjoint_kind(ASYM, SEC), ps);
     const int total = uniform(ps.pre[ps.n]);
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         const int i = find_slot(ps, u);
@@ -155,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void kb_adjoint(const SlotDev *tab,
         if (!running(d)) continue;
         const int local = local_unit(ps, i, u);
         if (local / d.P.K >= d.st.S || d.P.cutoff == 0.0) continue;
-        adjoint_phase<ASYM>(d.P, d.st, local / d.P.K, local % d.P.K, red);
+        adjoint_phase<ASYM, SEC>(d.P, d.st, local / d.P.K, local % d.P.K, red);
         __syncthreads();
     }
 }
@@ -210,16 +213,28 @@ __global__ void kb_advance(const SlotDev *tab, const SchedDev *sch) {
 }
 
 hipError_t launch_batch_step(const SlotDev *tab, const SchedDev *sch,
-                             hipStream_t s) {
+                             hipStream_t s, bool sec) {
     kb_sample<<<kGridSmall, 256, 0, s>>>(tab, sch);
-    kb_windows<<<kGridLarge, 256, 0, s>>>(tab, sch);
-    kb_plan<<<kGridLarge, 256, 0, s>>>(tab, sch);
-    kb_fused<true, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-    kb_fused<false, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-    kb_fused<true, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-    kb_fused<false, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-    kb_adjoint<false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-    kb_adjoint<true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    kb_windows<false><<<kGridLarge, 256, 0, s>>>(tab, sch);
+    if (sec) kb_windows<true><<<kGridLarge, 256, 0, s>>>(tab, sch);
+    kb_plan<false><<<kGridLarge, 256, 0, s>>>(tab, sch);
+    if (sec) kb_plan<true><<<kGridLarge, 256, 0, s>>>(tab, sch);
+    kb_fused<true, false, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    kb_fused<false, false, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    kb_fused<true, true, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    kb_fused<false, true, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    if (sec) {
+        kb_fused<true, false, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+        kb_fused<false, false, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+        kb_fused<true, true, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+        kb_fused<false, true, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    }
+    kb_adjoint<false, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    kb_adjoint<true, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    if (sec) {
+        kb_adjoint<false, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+        kb_adjoint<true, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    }
     kb_elbo<<<kGridElbo, 1024, 0, s>>>(tab, sch);
     kb_grad_adam<<<kGridLarge, 256, 0, s>>>(tab, sch);
     kb_advance<<<1, 1024, 0, s>>>(tab, sch);

@@ -32,6 +32,7 @@ struct Job {
     double cutoff = 0.0;
     double lambda_h = 0.0, mu_sd = 0.03, w_shape = 3.0, w_rate = 100.0;
     int D = 4;                   // latent types per phase (5: asymmetric)
+    int width_law = 0;           // 1: full width w sec(rho / 2)
     double alpha_mean = 1.0, alpha_sd = 0.2;
     // run
     int S = 1, steps = 1;

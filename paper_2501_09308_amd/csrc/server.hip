@@ -43,6 +43,7 @@ xrdvi_problem_desc job_desc(const Job &j) {
     d.prior.alpha_mean = j.alpha_mean;
     d.prior.alpha_sd = j.alpha_sd;
     d.asymmetric = j.D == 5;
+    d.width_law = j.width_law;
     return d;
 }
 
@@ -56,7 +57,8 @@ SlotLayout slot_layout(const Job &j) {
     const int T = j.off[j.K];
     L.prob = 0;
     L.step = a256(problem_bytes(j.N, j.K, T));
-    const StepShape sh{num_tiles(j.N), j.K, T, j.S, j.N, j.D, j.cutoff == 0.0};
+    const StepShape sh{num_tiles(j.N), j.K, T, j.S, j.N, j.D, j.cutoff == 0.0,
+                       j.width_law != 0};
     L.state = L.step + a256(step_bytes(sh));
     L.trace = L.state + a256(sizeof(double) * 6 * j.D * (size_t)j.K);
     L.total = L.trace + a256(sizeof(double) * (size_t)j.steps);
@@ -88,8 +90,10 @@ class GpuExecutor : public Executor {
     ~GpuExecutor() override {
         (void)hipSetDevice(device_);
         (void)hipStreamSynchronize(stream_);
-        if (gexec_) (void)hipGraphExecDestroy(gexec_);
-        if (graph_) (void)hipGraphDestroy(graph_);
+        for (int v = 0; v < 2; ++v) {
+            if (gexec_[v]) (void)hipGraphExecDestroy(gexec_[v]);
+            if (graph_[v]) (void)hipGraphDestroy(graph_[v]);
+        }
         if (d_tab_) (void)hipFree(d_tab_);
         if (d_sch_) (void)hipFree(d_sch_);
         if (d_steps_) (void)hipFree(d_steps_);
@@ -148,6 +152,9 @@ class GpuExecutor : public Executor {
         std::vector<std::pair<int, uint64_t>> members;
         for (const Job *j : active) members.emplace_back(j->slot, j->ticket);
         std::sort(members.begin(), members.end());
+        // the sec-law kernels run only while such an analysis is resident
+        bool sec = false;
+        for (const auto &m : members) sec = sec || h_tab_[m.first].P.sec != 0;
         hipError_t e = hipSuccess;
         if (changed || members != members_) {
             members_ = members;
@@ -167,12 +174,12 @@ class GpuExecutor : public Executor {
         }
         if (e == hipSuccess) {
             if (use_graph_) {
-                if (!gexec_) e = capture();
+                if (!gexec_[sec]) e = capture(sec);
                 for (int done = 0; e == hipSuccess && done < steps; done += graph_steps_)
-                    e = hipGraphLaunch(gexec_, stream_);
+                    e = hipGraphLaunch(gexec_[sec], stream_);
             } else {
                 for (int i = 0; e == hipSuccess && i < steps; ++i)
-                    e = launch_batch_step(d_tab_, d_sch_, stream_);
+                    e = launch_batch_step(d_tab_, d_sch_, stream_, sec);
             }
         }
         if (e == hipSuccess)
@@ -215,11 +222,12 @@ class GpuExecutor : public Executor {
     }
 
     // One graph holding graph_steps_ batched steps; kernels read the slot
-    // table and work prefix from fixed device buffers.
-    hipError_t capture() {
+    // table and work prefix from fixed device buffers.  Two variants: with
+    // and without the sec-law kernels.
+    hipError_t capture(bool sec) {
         hipError_t e = hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal);
         for (int i = 0; e == hipSuccess && i < graph_steps_; ++i)
-            e = launch_batch_step(d_tab_, d_sch_, stream_);
+            e = launch_batch_step(d_tab_, d_sch_, stream_, sec);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(stream_, &g);
         if (e == hipSuccess) e = e2;
@@ -227,8 +235,8 @@ class GpuExecutor : public Executor {
             if (g) (void)hipGraphDestroy(g);
             return e;
         }
-        graph_ = g;
-        return hipGraphInstantiate(&gexec_, graph_, nullptr, nullptr, 0);
+        graph_[sec] = g;
+        return hipGraphInstantiate(&gexec_[sec], graph_[sec], nullptr, nullptr, 0);
     }
 
     int device_;
@@ -243,8 +251,8 @@ class GpuExecutor : public Executor {
     int *d_steps_ = nullptr;
     int h_steps_[kMaxSlots] = {};
     std::vector<std::pair<int, uint64_t>> members_;
-    hipGraph_t graph_ = nullptr;
-    hipGraphExec_t gexec_ = nullptr;
+    hipGraph_t graph_[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec_[2] = {nullptr, nullptr};
 };
 
 // Validates a request and builds the job (host copies, default init).
@@ -273,6 +281,7 @@ int make_job(const xrdvi_request *r, std::unique_ptr<Job> *out) {
     j->w_shape = p.prior.w_shape;
     j->w_rate = p.prior.w_rate;
     j->D = latent_types(p);
+    j->width_law = p.width_law;
     j->alpha_mean = p.prior.alpha_mean;
     j->alpha_sd = p.prior.alpha_sd;
     j->S = r->S;

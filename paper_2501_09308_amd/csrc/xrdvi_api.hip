@@ -68,6 +68,7 @@ size_t step_bytes(const StepShape &sh) {
     b += align256(asym ? sizeof(int2) * S * nt * K : 4);  // rng2
     b += align256(sizeof(float) * S * (size_t)sh.N);  // rres
     b += align256(sizeof(double) * NS * K * S);     // pw
+    b += align256(sh.sec ? sizeof(float4) * S * (size_t)std::max(sh.T, 1) : 4);  // psec
     return b;
 }
 
@@ -95,6 +96,7 @@ StepDev carve_step(void *base, const StepShape &sh) {
     st.rng2 = (int2 *)take(asym ? sizeof(int2) * S * nt * K : 4);
     st.rres = (float *)take(sizeof(float) * S * (size_t)sh.N);
     st.pw = (double *)take(sizeof(double) * NS * K * S);
+    st.psec = (float4 *)take(sh.sec ? sizeof(float4) * S * (size_t)std::max(sh.T, 1) : 4);
     return st;
 }
 
@@ -159,6 +161,7 @@ hipError_t upload_problem(const xrdvi_problem_desc &d, double lambda,
     P = ProbDev{};
     P.N = N; P.K = K; P.T = T; P.ntiles = num_tiles(N);
     P.D = latent_types(d);
+    P.sec = d.width_law;
     P.cutoff = d.cutoff;
     P.x0 = d.x[0];
     P.inv_dx = N > 1 ? (double)(N - 1) / (d.x[N - 1] - d.x[0]) : 0.0;
@@ -270,6 +273,13 @@ int validate_desc(const xrdvi_problem_desc *d, double *lambda_out,
                           || !std::isfinite(pr.alpha_sd)))
         return fail(XRDVI_EINVAL,
                     "prior.alpha_mean must be finite and prior.alpha_sd > 0");
+    if (d->width_law != 0 && d->width_law != 1)
+        return fail(XRDVI_EINVAL, "width_law must be 0 or 1");
+    if (d->width_law == 1)
+        for (int j = 0; j < T; ++j)
+            if (!(d->peak_pos[j] > 0.0) || !(d->peak_pos[j] < 180.0))
+                return fail(XRDVI_EINVAL,
+                            "peak_pos must lie inside (0, 180) with width_law 1");
     double lam = pr.lambda_h;
     double m = -INFINITY;
     for (int i = 0; i < d->N; ++i) m = std::max(m, d->y[i] - d->bg[i]);
@@ -494,8 +504,7 @@ int xrdvi_profile(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     StepDev st = carve_step(ctx->ws, step_shape(P, S));
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(launch_phi_consts(P, S, phi, st.pk, st.pkr, s), "phi constants");
-    if (P.cutoff > 0.0)
-        HIP_TRY(launch_windows(P, S, phi, st.lo, st.hi, nullptr, s), "window plan");
+    HIP_TRY(launch_peak_plan(P, st, phi, s), "window plan");
     HIP_TRY(launch_plan(P, st, phi, s), "tile plan");
     HIP_TRY(timed_fused(ctx, P, st, false, f_out, s), "profile");
     return XRDVI_OK;
@@ -534,8 +543,7 @@ int xrdvi_elbo_fwd(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     hipStream_t s = static_cast<hipStream_t>(stream);
     tape->has_grad = false;
     HIP_TRY(launch_sample(P, st, loc, logscale, eps, seed, step, s), "sample");
-    if (P.cutoff > 0.0)
-        HIP_TRY(launch_windows(P, S, st.phi, st.lo, st.hi, nullptr, s), "window plan");
+    HIP_TRY(launch_peak_plan(P, st, st.phi, s), "window plan");
     HIP_TRY(launch_plan(P, st, st.phi, s), "tile plan");
     HIP_TRY(timed_fused(ctx, P, st, need_grad != 0, nullptr, s),
             "fused profile/adjoint");

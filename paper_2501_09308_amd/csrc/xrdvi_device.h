@@ -23,6 +23,14 @@
 // it keeps unit area; the same formulas hold with q2 = 2 (x - rho) / (A w)
 // and the prefactors multiplied by 2 / (1 + alpha).  Each phase then has a
 // fifth latent, alpha = exp(z_alpha) with a normal prior.
+//
+// Angle-dependent width (Appendix A.2 uses sec(x) = 1/cos(x) in the lost
+// width formula): with the sec law the full width of peak m of phase k is
+// W = w sec(theta), theta = rho / 2, taken as w / |cos(rho pi / 360)|.
+// Writing c = |cos theta|, the peak is the same function of
+// q2 = 2 c (x - rho) / (A w) with its intensity scaled by c, so the phase
+// constants stay per phase and each peak carries (c, I c); the shift's
+// gradient gains the term of dW/drho = W tan(theta) pi / 360.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -46,6 +54,7 @@ constexpr double kCL = 0.63661977236758134308;   // 2 / pi
 constexpr double kLn2 = 0.69314718055994530942;
 constexpr double kLn2Pi = 1.83787706640934548356;  // ln(2 pi)
 constexpr double kTwoPi = 6.28318530717958647693;
+constexpr double kHalfDegRad = 3.14159265358979323846 / 360.0;  // rad per deg / 2
 
 // A prepared problem in device memory (peaks ordered by position within
 // each phase).
@@ -53,6 +62,7 @@ struct ProbDev {
     int N, K, T, ntiles;
     int D;                            // latent types per phase: 4, or 5 with
                                       // the asymmetry alpha
+    int sec;                          // 1: width w sec(rho / 2); 0: width w
     double cutoff;
     double lambda, mu_sd, w_shape, w_rate;
     double a_mean, a_sd;              // normal prior on alpha (D = 5)
@@ -90,6 +100,8 @@ struct StepDev {
     int2 *rng2;       // [S][ntiles][K] (jr, jl) for D = 5: peaks before jr
                       // lie at or below every point of the tile, peaks from
                       // jl above every point
+    float4 *psec;     // [S][T] sec width law, per (sample, peak):
+                      // (c, I c, tan(theta) (pi/360) w, 0), c = |cos theta|
     float *rres;      // [S][N] residual y/f - 1 (windowed mode)
     double *pw;       // [K][S][num_sums] adjoint sums per (phase, sample)
                       // (windowed mode)
@@ -230,15 +242,25 @@ __device__ inline int upper_bound_x(const double *x, int n, double x0,
     return grid_bound<true>(x, n, x0, inv_dx, v);
 }
 
-// Grid range [lo, hi) with rho - c w <= x_i <= rho + c w (rho + (c w) alpha
-// for asymmetric peaks, alpha > 0; pass 1 otherwise); each bound is one
-// rounded FP64 operation (no contraction), as in the model's definition.
+// Full width of a peak centred at rho: w, or w / |cos(rho pi / 360)| with
+// the sec law (SEC).
+template <bool SEC>
+__device__ __forceinline__ double peak_width(double rho, double w) {
+#pragma clang fp contract(off)
+    return SEC ? w / fabs(cos(rho * kHalfDegRad)) : w;
+}
+
+// Grid range [lo, hi) with rho - c W <= x_i <= rho + c W (rho + (c W) alpha
+// for asymmetric peaks, alpha > 0; pass 1 otherwise), W the peak's full
+// width; each bound is one rounded FP64 operation (no contraction), as in
+// the model's definition.
+template <bool SEC>
 __device__ inline int2 window_of(const ProbDev &P, double p, double mu,
                                  double w, double alpha) {
 #pragma clang fp contract(off)
     if (P.cutoff == 0.0) return make_int2(0, P.N);
     const double rho = p + mu;
-    const double hw = P.cutoff * w;
+    const double hw = P.cutoff * peak_width<SEC>(rho, w);
     const double a = rho - hw;
     const double b = rho + (P.D == 5 ? hw * alpha : hw);
     const int lo = lower_bound_x(P.x, P.N, P.x0, P.inv_dx, a);
@@ -299,28 +321,78 @@ __device__ inline int first_centre_above(const double *p, int a, int b,
     return a;
 }
 
+// With the sec law a peak's reach [rho - R W, rho + R alpha W] has bounds
+// that move with rho at slopes 1 - R W tau and 1 + R alpha W tau
+// (tau = tan(theta) pi / 360).  For centres inside (-180, 180) deg, W tau
+// increases with rho, so both bounds are monotone over a phase (and the
+// searches over its sorted peaks valid) when the slopes are positive at the
+// last and the first centre respectively.
+__device__ inline bool sec_monotone(double rf, double rl, double w, double R,
+                                    double alpha) {
+#pragma clang fp contract(off)
+    if (!(rf > -180.0) || !(rl < 180.0)) return false;
+    const double tf = rf * kHalfDegRad, tl = rl * kHalfDegRad;
+    const double up = 1.0 + R * alpha * (w / fabs(cos(tf))) * tan(tf) * kHalfDegRad;
+    const double dn = 1.0 - R * (w / fabs(cos(tl))) * tan(tl) * kHalfDegRad;
+    return up > 0.0 && dn > 0.0;
+}
+
+// First j in [a, b) with pred(j) true (pred false then true over [a, b)).
+template <typename F>
+__device__ inline int first_true(int a, int b, F pred) {
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (pred(mid)) b = mid; else a = mid + 1;
+    }
+    return a;
+}
+
 // Range entry of (sample s, tile t, phase k); phi: [S][D][K].  For
 // asymmetric peaks *side receives (jr, jl) with ga <= jr <= jl <= gb.
+// Ranges may be wider than needed (the windowed kernels mask each peak by
+// its exact window); with the sec law they cover the whole phase when its
+// bounds are not monotone.
+template <bool SEC>
 __device__ inline int4 tile_range(const ProbDev &P, const StepDev &st,
                                   const double *phi, int s, int t, int k,
                                   int2 *side) {
+#pragma clang fp contract(off)
     const int a = P.off[k], b = P.off[k + 1];
     const int i0 = t * kTile, i1 = min(i0 + kTile, P.N);
+    const double *ph = phi + (size_t)s * P.D * P.K;
+    const double mu = ph[P.K + k], w = ph[2 * P.K + k];
+    const double alpha = P.D == 5 ? ph[4 * P.K + k] : 1.0;
+    bool win_mono = true, g_mono = true;
+    if (SEC && a < b) {
+        const double rf = P.pos[a] + mu, rl = P.pos[b - 1] + mu;
+        win_mono = sec_monotone(rf, rl, w, P.cutoff, alpha);
+        g_mono = sec_monotone(rf, rl, w, kGaussReach, alpha);
+    }
     int ja = a, jb = b;
-    if (P.cutoff > 0.0) {
+    if (P.cutoff > 0.0 && win_mono) {
         const int *lo = st.lo + (size_t)s * P.T;
         const int *hi = st.hi + (size_t)s * P.T;
         ja = first_greater(hi, a, b, i0);
         jb = first_not_less(lo, ja, b, i1);
     }
-    const double *ph = phi + (size_t)s * P.D * P.K;
-    const double mu = ph[P.K + k], w = ph[2 * P.K + k];
-    const double alpha = P.D == 5 ? ph[4 * P.K + k] : 1.0;
-    const double reach = kGaussReach * w;       // below rho
-    const double reach_hi = reach * alpha;      // above rho
-    // Gaussian relevant: p + mu + reach_hi >= x[i0], p + mu - reach <= x[i1-1]
-    const int ga = first_not_less_d(P.pos, ja, jb, P.x[i0] - mu - reach_hi);
-    const int gb = first_greater_d(P.pos, ga, jb, P.x[i1 - 1] - mu + reach);
+    int ga = ja, gb = jb;
+    if (!SEC) {
+        const double reach = kGaussReach * w;       // below rho
+        const double reach_hi = reach * alpha;      // above rho
+        // Gaussian relevant: p + mu + reach_hi >= x[i0], p + mu - reach <= x[i1-1]
+        ga = first_not_less_d(P.pos, ja, jb, P.x[i0] - mu - reach_hi);
+        gb = first_greater_d(P.pos, ga, jb, P.x[i1 - 1] - mu + reach);
+    } else if (g_mono) {
+        const double xa = P.x[i0], xb = P.x[i1 - 1];
+        ga = first_true(ja, jb, [&](int j) {
+            const double rho = P.pos[j] + mu;
+            return rho + kGaussReach * peak_width<SEC>(rho, w) * alpha >= xa;
+        });
+        gb = first_true(ga, jb, [&](int j) {
+            const double rho = P.pos[j] + mu;
+            return rho - kGaussReach * peak_width<SEC>(rho, w) > xb;
+        });
+    }
     if (side) {
         const int jr = first_centre_above(P.pos, ga, gb, mu, P.x[i0]);
         const int jl = first_centre_above(P.pos, jr, gb, mu, P.x[i1 - 1]);
@@ -383,31 +455,42 @@ struct PeakMask {
     }
 };
 
-// Per-peak data of one phase seen by a segment loop.
-// One peak as a segment loop sees it: tile-relative position, intensity
-// and (windowed mode) its grid window [lo, hi).
+// One peak as a segment loop sees it: tile-relative position, intensity,
+// (windowed mode) its grid window [lo, hi) and, with the sec width law,
+// c = |cos theta| and tw = tan(theta) (pi/360) w (the intensity is then
+// I c).
 struct PeakRec {
     float pt, I;
     int lo, hi;
+    float c, tw;
 };
 
 struct SegPeaks {
     cptr<float> pt;       // tile-relative positions
     cptr<float> inten;
     cptr<int> wlo, whi;   // windows (WIN)
+    cptr<float> sec;      // per-sample sec-law records, 4 floats each (SEC)
     // scalar loads (unused fields are never loaded)
+    template <bool SEC>
     __device__ __forceinline__ PeakRec rec(int j) const {
-        return PeakRec{pt[j], inten[j], wlo[j], whi[j]};
+        if (SEC)
+            return PeakRec{pt[j], sec[4 * j + 1], wlo[j], whi[j], sec[4 * j],
+                           sec[4 * j + 2]};
+        return PeakRec{pt[j], inten[j], wlo[j], whi[j], 1.f, 0.f};
     }
 };
 
-// Peak records staged in LDS by the windowed tile (record j at pd[j + shift]).
+// Peak records staged in LDS by the windowed tile (record j at pd[j + shift],
+// its sec-law c at pc[j + shift]).
 struct LdsPeaks {
     const float4 *pd;
+    const float *pc;
     int shift;
+    template <bool SEC>
     __device__ __forceinline__ PeakRec rec(int j) const {
         const float4 v = pd[j + shift];
-        return PeakRec{v.x, v.y, __float_as_int(v.z), __float_as_int(v.w)};
+        return PeakRec{v.x, v.y, __float_as_int(v.z), __float_as_int(v.w),
+                       SEC ? pc[j + shift] : 1.f, 0.f};
     }
 };
 
@@ -426,7 +509,15 @@ __device__ __forceinline__ float seg_q2(float ptj, float iw2, float iw2r,
     return ql >= 0.f ? qr : ql;
 }
 
-template <bool WIN, bool GAUSS, int SIDE, typename PK>
+// Sec law: q2 = c 2 (x - rho) / (A w), the constant-width q2 (one rounding
+// of a fused multiply-add, accurate near the peak) scaled by c.
+template <int SIDE>
+__device__ __forceinline__ float seg_q2_sec(float c, float ptj, float iw2,
+                                            float iw2r, float uq, float uqr) {
+    return c * seg_q2<SIDE>(ptj, iw2, iw2r, uq, uqr);
+}
+
+template <bool WIN, bool GAUSS, int SIDE, bool SEC, typename PK>
 __device__ __forceinline__ void fwd_segment(const PK &pk, int j0, int j1,
                                             const int (&idx)[kPPL],
                                             const float (&uq)[kPPL],
@@ -436,14 +527,15 @@ __device__ __forceinline__ void fwd_segment(const PK &pk, int j0, int j1,
                                             float (&accG)[kPPL]) {
 #pragma unroll 2
     for (int j = j0; j < j1; ++j) {
-        const PeakRec r = pk.rec(j);
+        const PeakRec r = pk.template rec<SEC>(j);
         const float ptj = r.pt;
         const float I = r.I;
         PeakMask<WIN> mk;
         if (WIN) { mk.lo = r.lo; mk.hi = r.hi; }
 #pragma unroll
         for (int p = 0; p < kPPL; ++p) {
-            const float q2 = seg_q2<SIDE>(ptj, iw2, iw2r, uq[p], uqr[p]);
+            const float q2 = SEC ? seg_q2_sec<SIDE>(r.c, ptj, iw2, iw2r, uq[p], uqr[p])
+                                 : seg_q2<SIDE>(ptj, iw2, iw2r, uq[p], uqr[p]);
             const float tt = mk.apply(idx[p], fmaf(q2, q2, 1.0f));
             accL[p] = fmaf(I, rcp_f32(tt), accL[p]);
             if (GAUSS) accG[p] = fmaf(I, exp2_f32(1.0f - tt), accG[p]);
@@ -463,24 +555,47 @@ struct Acc6 {
     }
 };
 
+// Sec law: the shift moves the centre and, through W(rho), the width, so
+// the mu sums take per-peak weights (side A: A = 1 below, alpha above):
+//   e1 += I e (c q2 + kG (2 ln2 q2^2 - 1)),  kG = A tw / (4 ln2),
+//   l1 += I l (c q2 l + kL (1 - 2 l)),       kL = A tw / 4,
+// which phase_grad turns into d/dmu exactly as the plain sums (c = 1,
+// tw = 0).  With q2^2 = tt - 1 the Gaussian weight is
+// c q2 + bG tt + gG, bG = A tw / 2, gG = -A tw (1/2 + 1/(4 ln2)).
+struct SecW {
+    float bG, gG, kL;
+    __device__ __forceinline__ static SecW of(float tws) {
+        constexpr float kInv4Ln2 = 0.36067376022224085f;   // 1 / (4 ln 2)
+        return SecW{0.5f * tws, -tws * (0.5f + kInv4Ln2), 0.25f * tws};
+    }
+};
+
 // Adds the peak terms of [j0, j1) to `lo` (points below the centres, or
-// symmetric peaks) or `hi` (points above).
-template <bool WIN, bool GAUSS, int SIDE>
+// symmetric peaks) or `hi` (points above).  ka: alpha of the phase (sec law
+// with asymmetric peaks; 1 otherwise).
+template <bool WIN, bool GAUSS, int SIDE, bool SEC>
 __device__ __forceinline__ void adj_segment(const SegPeaks &pk, int j0, int j1,
                                             const int (&idx)[kPPL],
                                             const float (&uq)[kPPL],
                                             const float (&uqr)[kPPL],
-                                            float iw2, float iw2r, Acc6 &lo,
-                                            Acc6 &hi) {
+                                            float iw2, float iw2r, float ka,
+                                            Acc6 &lo, Acc6 &hi) {
 #pragma unroll 2
     for (int j = j0; j < j1; ++j) {
-        const float ptj = pk.pt[j];
-        const float I = pk.inten[j];
+        const PeakRec r = pk.template rec<SEC>(j);
+        const float ptj = r.pt;
+        const float I = r.I;
+        SecW wl{0.f, 0.f, 0.f}, wh{0.f, 0.f, 0.f};
+        if (SEC) {
+            if (SIDE != kAbove) wl = SecW::of(r.tw);
+            if (SIDE != kBelow) wh = SecW::of(r.tw * ka);
+        }
         PeakMask<WIN> mk;
-        if (WIN) { mk.lo = pk.wlo[j]; mk.hi = pk.whi[j]; }
+        if (WIN) { mk.lo = r.lo; mk.hi = r.hi; }
 #pragma unroll
         for (int p = 0; p < kPPL; ++p) {
-            const float q2 = seg_q2<SIDE>(ptj, iw2, iw2r, uq[p], uqr[p]);
+            const float q2 = SEC ? seg_q2_sec<SIDE>(r.c, ptj, iw2, iw2r, uq[p], uqr[p])
+                                 : seg_q2<SIDE>(ptj, iw2, iw2r, uq[p], uqr[p]);
             const float tt = mk.apply(idx[p], fmaf(q2, q2, 1.0f));
             const float l = rcp_f32(tt);
             const float Il = I * l;
@@ -494,27 +609,53 @@ __device__ __forceinline__ void adj_segment(const SegPeaks &pk, int j0, int j1,
                 Acc6 &a = SIDE == kAbove ? hi : lo;
                 a.l0[p] += Il;
                 a.l2[p] += Ill;
-                a.l1[p] = fmaf(Ill, q2, a.l1[p]);
+                if (SEC) {
+                    const SecW &sw = SIDE == kAbove ? wh : wl;
+                    a.l1[p] = fmaf(Ill, fmaf(r.c, q2, -2.f * sw.kL), a.l1[p]);
+                    a.l1[p] = fmaf(Il, sw.kL, a.l1[p]);
+                } else {
+                    a.l1[p] = fmaf(Ill, q2, a.l1[p]);
+                }
                 if (GAUSS) {
                     a.e0[p] += Ie;
-                    a.e1[p] += Ieq;
+                    if (SEC) {
+                        const SecW &sw = SIDE == kAbove ? wh : wl;
+                        a.e1[p] = fmaf(Ie, fmaf(r.c, q2, fmaf(sw.bG, tt, sw.gG)),
+                                       a.e1[p]);
+                    } else {
+                        a.e1[p] += Ieq;
+                    }
                     a.e2[p] = fmaf(Ieq, q2, a.e2[p]);
                 }
             } else {
-                const float Illq = Ill * q2, Ieqq = Ieq * q2;
-                const float fu = fmaf(-ptj, iw2, uq[p]) >= 0.f ? 1.f : 0.f;
+                const float Ieqq = Ieq * q2;
+                const bool up = fmaf(-ptj, iw2, uq[p]) >= 0.f;
+                const float fu = up ? 1.f : 0.f;
                 const float fd = 1.f - fu;
+                float m1L, m1G = 0.f;
+                if (SEC) {
+                    const float kL = up ? wh.kL : wl.kL;
+                    m1L = fmaf(Ill, fmaf(r.c, q2, -2.f * kL), Il * kL);
+                    if (GAUSS) {
+                        const float bG = up ? wh.bG : wl.bG;
+                        const float gG = up ? wh.gG : wl.gG;
+                        m1G = Ie * fmaf(r.c, q2, fmaf(bG, tt, gG));
+                    }
+                } else {
+                    m1L = Ill * q2;
+                    m1G = Ieq;
+                }
                 hi.l0[p] = fmaf(fu, Il, hi.l0[p]);
                 lo.l0[p] = fmaf(fd, Il, lo.l0[p]);
                 hi.l2[p] = fmaf(fu, Ill, hi.l2[p]);
                 lo.l2[p] = fmaf(fd, Ill, lo.l2[p]);
-                hi.l1[p] = fmaf(fu, Illq, hi.l1[p]);
-                lo.l1[p] = fmaf(fd, Illq, lo.l1[p]);
+                hi.l1[p] = fmaf(fu, m1L, hi.l1[p]);
+                lo.l1[p] = fmaf(fd, m1L, lo.l1[p]);
                 if (GAUSS) {
                     hi.e0[p] = fmaf(fu, Ie, hi.e0[p]);
                     lo.e0[p] = fmaf(fd, Ie, lo.e0[p]);
-                    hi.e1[p] = fmaf(fu, Ieq, hi.e1[p]);
-                    lo.e1[p] = fmaf(fd, Ieq, lo.e1[p]);
+                    hi.e1[p] = fmaf(fu, m1G, hi.e1[p]);
+                    lo.e1[p] = fmaf(fd, m1G, lo.e1[p]);
                     hi.e2[p] = fmaf(fu, Ieqq, hi.e2[p]);
                     lo.e2[p] = fmaf(fd, Ieqq, lo.e2[p]);
                 }
@@ -585,7 +726,7 @@ __device__ __forceinline__ void tile_points(const ProbDev &P, const StepDev &st,
     }
 }
 
-template <bool WIN, bool GRAD, bool ASYM>
+template <bool WIN, bool GRAD, bool ASYM, bool SEC>
 __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
                            float *f_out, FusedSmem &sm) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -608,6 +749,8 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
     sp.inten = as_const(P.inten);
     sp.wlo = as_const(st.lo + (size_t)s * P.T);
     sp.whi = as_const(st.hi + (size_t)s * P.T);
+    sp.sec = SEC ? as_const(reinterpret_cast<const float *>(st.psec + (size_t)s * P.T))
+                 : nullptr;
 
     float u[kPPL];
     int idx[kPPL];
@@ -639,15 +782,15 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
         }
         if (ASYM) {
             const int jr = rg2[2 * k], jl = rg2[2 * k + 1];
-            fwd_segment<WIN, false, kAbove>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
-            fwd_segment<WIN, true, kAbove>(sp, ga, jr, idx, uq, uqr, iw2, iw2r, accL, accG);
-            fwd_segment<WIN, true, kBoth>(sp, jr, jl, idx, uq, uqr, iw2, iw2r, accL, accG);
-            fwd_segment<WIN, true, kBelow>(sp, jl, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
-            fwd_segment<WIN, false, kBelow>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, false, kAbove, SEC>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, true, kAbove, SEC>(sp, ga, jr, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, true, kBoth, SEC>(sp, jr, jl, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, true, kBelow, SEC>(sp, jl, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, false, kBelow, SEC>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
         } else {
-            fwd_segment<WIN, false, kBelow>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
-            fwd_segment<WIN, true, kBelow>(sp, ga, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
-            fwd_segment<WIN, false, kBelow>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, false, kBelow, SEC>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, true, kBelow, SEC>(sp, ga, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, false, kBelow, SEC>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
         }
 #pragma unroll
         for (int p = 0; p < kPPL; ++p)
@@ -685,20 +828,21 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
             uq[p] = (u[p] - mu) * iw2;
             uqr[p] = ASYM ? (u[p] - mu) * iw2r : uq[p];
         }
+        const float ka = ASYM && SEC ? iw2 / iw2r : 1.f;   // alpha
         Acc6 lo, hi;
         lo.zero();
         if (ASYM) {
             hi.zero();
             const int jr = rg2[2 * k], jl = rg2[2 * k + 1];
-            adj_segment<WIN, false, kAbove>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, lo, hi);
-            adj_segment<WIN, true, kAbove>(sp, ga, jr, idx, uq, uqr, iw2, iw2r, lo, hi);
-            adj_segment<WIN, true, kBoth>(sp, jr, jl, idx, uq, uqr, iw2, iw2r, lo, hi);
-            adj_segment<WIN, true, kBelow>(sp, jl, gb, idx, uq, uqr, iw2, iw2r, lo, hi);
-            adj_segment<WIN, false, kBelow>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, lo, hi);
+            adj_segment<WIN, false, kAbove, SEC>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
+            adj_segment<WIN, true, kAbove, SEC>(sp, ga, jr, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
+            adj_segment<WIN, true, kBoth, SEC>(sp, jr, jl, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
+            adj_segment<WIN, true, kBelow, SEC>(sp, jl, gb, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
+            adj_segment<WIN, false, kBelow, SEC>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
         } else {
-            adj_segment<WIN, false, kBelow>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, lo, hi);
-            adj_segment<WIN, true, kBelow>(sp, ga, gb, idx, uq, uqr, iw2, iw2r, lo, hi);
-            adj_segment<WIN, false, kBelow>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, lo, hi);
+            adj_segment<WIN, false, kBelow, SEC>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
+            adj_segment<WIN, true, kBelow, SEC>(sp, ga, gb, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
+            adj_segment<WIN, false, kBelow, SEC>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
         }
         store_sums(lo, rres, lane, dst);
         if (ASYM) store_sums(hi, rres, lane, dst + 6);
@@ -722,6 +866,8 @@ constexpr int kWinPeaks = 1024;     // staged peak records per chunk
 // scalar loads (3501 points, K = 50, S = 64: 22.6 us instead of 25.0 us).
 constexpr int kWinStageK = 128;
 
+// SEC: the staged records also hold each peak's sec-law c (pc).
+template <bool SEC>
 struct WinSmem {
     int4 rg[kWinChunk];
     float4 pk[kWinChunk];
@@ -730,20 +876,22 @@ struct WinSmem {
     int off[kWinChunk];
     int wsum[kWaves];
     float4 pd[kWinPeaks];
+    float pc[SEC ? kWinPeaks : 1];
     float sig[kWaves][kTile];
     float rres[kTile];
     double red[kWaves];
 };
 
 // Shared memory of a windowed tile of either kind.
+template <bool SEC>
 union WinTileSmem {
     FusedSmem f;
-    WinSmem w;
+    WinSmem<SEC> w;
 };
 
-template <bool ASYM>
+template <bool ASYM, bool SEC>
 __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
-                         float *f_out, WinSmem &sm) {
+                         float *f_out, WinSmem<SEC> &sm) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -756,11 +904,13 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
     const float *ptt = P.pt + (size_t)t * P.T;
     const int *wlo = st.lo + (size_t)s * P.T;
     const int *whi = st.hi + (size_t)s * P.T;
+    const float4 *psec = SEC ? st.psec + (size_t)s * P.T : nullptr;
     SegPeaks sp;
     sp.pt = as_const(ptt);
     sp.inten = as_const(P.inten);
     sp.wlo = as_const(wlo);
     sp.whi = as_const(whi);
+    sp.sec = as_const(reinterpret_cast<const float *>(psec));
 
     float u[kPPL];
     int idx[kPPL];
@@ -802,7 +952,13 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
         if (tid < nk) sm.off[tid] = excl;
         for (int q = 0; q < cnt && excl + q < kWinPeaks; ++q) {
             const int j = ja + q;
-            sm.pd[excl + q] = make_float4(ptt[j], P.inten[j], __int_as_float(wlo[j]),
+            float I = P.inten[j];
+            if (SEC) {
+                const float4 v = psec[j];
+                I = v.y;
+                sm.pc[excl + q] = v.x;
+            }
+            sm.pd[excl + q] = make_float4(ptt[j], I, __int_as_float(wlo[j]),
                                           __int_as_float(whi[j]));
         }
         __syncthreads();
@@ -833,19 +989,19 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
             }
             auto run = [&](const auto &pks) {
                 if (ASYM) {
-                    fwd_segment<true, false, kAbove>(pks, ja_k, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
-                    fwd_segment<true, true, kAbove>(pks, ga, jr, idx, uq, uqr, iw2, iw2r, accL, accG);
-                    fwd_segment<true, true, kBoth>(pks, jr, jl, idx, uq, uqr, iw2, iw2r, accL, accG);
-                    fwd_segment<true, true, kBelow>(pks, jl, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
-                    fwd_segment<true, false, kBelow>(pks, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
+                    fwd_segment<true, false, kAbove, SEC>(pks, ja_k, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
+                    fwd_segment<true, true, kAbove, SEC>(pks, ga, jr, idx, uq, uqr, iw2, iw2r, accL, accG);
+                    fwd_segment<true, true, kBoth, SEC>(pks, jr, jl, idx, uq, uqr, iw2, iw2r, accL, accG);
+                    fwd_segment<true, true, kBelow, SEC>(pks, jl, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
+                    fwd_segment<true, false, kBelow, SEC>(pks, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
                 } else {
-                    fwd_segment<true, false, kBelow>(pks, ja_k, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
-                    fwd_segment<true, true, kBelow>(pks, ga, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
-                    fwd_segment<true, false, kBelow>(pks, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
+                    fwd_segment<true, false, kBelow, SEC>(pks, ja_k, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
+                    fwd_segment<true, true, kBelow, SEC>(pks, ga, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
+                    fwd_segment<true, false, kBelow, SEC>(pks, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
                 }
             };
             const int base = __builtin_amdgcn_readfirstlane(sm.off[kl]);
-            if (base + (jb - ja_k) <= kWinPeaks) run(LdsPeaks{sm.pd, base - ja_k});
+            if (base + (jb - ja_k) <= kWinPeaks) run(LdsPeaks{sm.pd, sm.pc, base - ja_k});
             else run(sp);
 #pragma unroll
             for (int p = 0; p < kPPL; ++p)
@@ -868,9 +1024,12 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
 // rounded to FP32 (its sign picks the side of an asymmetric peak).  Six
 // sums (twelve: six per side) accumulate per lane over the wave's peaks,
 // are reduced over the wave, then over the waves in fixed order.
-template <bool ASYM>
+// SEC: iw2 and iw2r carry the peak's c, and wl / wh are the mu-sum weights
+// of the two sides (see SecW).
+template <bool ASYM, bool SEC>
 __device__ __forceinline__ void adj_point(bool valid, float R, double d,
-                                          float iw2, float iw2r,
+                                          float iw2, float iw2r, float c,
+                                          const SecW &wl, const SecW &wh,
                                           float (&acc)[ASYM ? 12 : 6]) {
     const bool up = ASYM && d >= 0.0;
     const float q2 = (float)d * (up ? iw2r : iw2);
@@ -884,29 +1043,45 @@ __device__ __forceinline__ void adj_point(bool valid, float R, double d,
         Re = R * exp2_f32(1.0f - tt);
         Req = Re * q2;
     }
+    float m1L, m1G = 0.f;
+    if (SEC) {
+        const float kL = up ? wh.kL : wl.kL;
+        m1L = fmaf(Rll, fmaf(c, q2, -2.f * kL), Rl * kL);
+        if (gauss) {
+            const float bG = up ? wh.bG : wl.bG;
+            const float gG = up ? wh.gG : wl.gG;
+            m1G = Re * fmaf(c, q2, fmaf(bG, tt, gG));
+        }
+    }
     if (!ASYM) {
         acc[3] += Rl;
         acc[5] += Rll;
-        acc[4] = fmaf(Rll, q2, acc[4]);
+        if (SEC) acc[4] += m1L;
+        else acc[4] = fmaf(Rll, q2, acc[4]);
         if (gauss) {
             acc[0] += Re;
-            acc[1] += Req;
+            if (SEC) acc[1] += m1G;
+            else acc[1] += Req;
             acc[2] = fmaf(Req, q2, acc[2]);
         }
     } else {
-        const float Rllq = Rll * q2, Reqq = Req * q2;
+        if (!SEC) {
+            m1L = Rll * q2;
+            m1G = Req;
+        }
+        const float Reqq = Req * q2;
         const float fu = up ? 1.f : 0.f, fd = 1.f - fu;
         acc[3] = fmaf(fd, Rl, acc[3]);
         acc[9] = fmaf(fu, Rl, acc[9]);
         acc[5] = fmaf(fd, Rll, acc[5]);
         acc[11] = fmaf(fu, Rll, acc[11]);
-        acc[4] = fmaf(fd, Rllq, acc[4]);
-        acc[10] = fmaf(fu, Rllq, acc[10]);
+        acc[4] = fmaf(fd, m1L, acc[4]);
+        acc[10] = fmaf(fu, m1L, acc[10]);
         if (gauss) {
             acc[0] = fmaf(fd, Re, acc[0]);
             acc[6] = fmaf(fu, Re, acc[6]);
-            acc[1] = fmaf(fd, Req, acc[1]);
-            acc[7] = fmaf(fu, Req, acc[7]);
+            acc[1] = fmaf(fd, m1G, acc[1]);
+            acc[7] = fmaf(fu, m1G, acc[7]);
             acc[2] = fmaf(fd, Reqq, acc[2]);
             acc[8] = fmaf(fu, Reqq, acc[8]);
         }
@@ -917,7 +1092,7 @@ __device__ __forceinline__ void adj_point(bool valid, float R, double d,
 // back to back, so one memory latency covers all of them.
 constexpr int kAdjPeaks = 4;
 
-template <bool ASYM>
+template <bool ASYM, bool SEC>
 __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
                                      int s, int k, double (*red)[12]) {
     constexpr int NS = ASYM ? 12 : 6;
@@ -933,6 +1108,9 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
     cptr<int> whi = as_const(st.hi + (size_t)s * P.T);
     cptr<double> pos = as_const(P.pos);
     cptr<float> inten = as_const(P.inten);
+    cptr<float> psec = SEC ? as_const(reinterpret_cast<const float *>(st.psec + (size_t)s * P.T))
+                           : nullptr;
+    const float ka = ASYM ? (float)ph[4 * K + k] : 1.f;
     const int a = P.off[k], b = P.off[k + 1];
     float acc[NS];
 #pragma unroll
@@ -940,7 +1118,7 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
     // wave wv takes peaks a + wv + kWaves * (kAdjPeaks * g + q), q < kAdjPeaks
     for (int j0 = a + wv; j0 < b; j0 += kWaves * kAdjPeaks) {
         int lo[kAdjPeaks], len[kAdjPeaks];
-        float I[kAdjPeaks];
+        float I[kAdjPeaks], cq[kAdjPeaks], tw[kAdjPeaks];
         double rho[kAdjPeaks];
         int span = 0;
 #pragma unroll
@@ -950,7 +1128,15 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
             const int jj = ok ? j : j0;
             lo[q] = wlo[jj];
             len[q] = ok ? whi[jj] - lo[q] : 0;
-            I[q] = inten[jj];
+            if (SEC) {
+                cq[q] = psec[4 * jj];
+                I[q] = psec[4 * jj + 1];
+                tw[q] = psec[4 * jj + 2];
+            } else {
+                cq[q] = 1.f;
+                I[q] = inten[jj];
+                tw[q] = 0.f;
+            }
             rho[q] = pos[jj] + mu;
             span = max(span, len[q]);
         }
@@ -968,8 +1154,16 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
                 d[q] = P.x[ii] - rho[q];
             }
 #pragma unroll
-            for (int q = 0; q < kAdjPeaks; ++q)
-                adj_point<ASYM>(valid[q], R[q], d[q], iw2, iw2r, acc);
+            for (int q = 0; q < kAdjPeaks; ++q) {
+                if (SEC)
+                    adj_point<ASYM, true>(valid[q], R[q], d[q], iw2 * cq[q],
+                                          iw2r * cq[q], cq[q], SecW::of(tw[q]),
+                                          SecW::of(tw[q] * ka), acc);
+                else
+                    adj_point<ASYM, false>(valid[q], R[q], d[q], iw2, iw2r, 1.f,
+                                           SecW{0.f, 0.f, 0.f}, SecW{0.f, 0.f, 0.f},
+                                           acc);
+            }
         }
     }
 #pragma unroll

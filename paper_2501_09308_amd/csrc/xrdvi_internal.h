@@ -20,8 +20,15 @@ hipError_t launch_sample(const ProbDev &P, const StepDev &st,
                          hipStream_t stream);
 hipError_t launch_phi_consts(const ProbDev &P, int S, const double *phi,
                              float4 *pk, float *pkr, hipStream_t stream);
+// Window plan of S samples (lo/hi NULL: none) under the problem's width
+// law and, with psec (sec law only), the sec-law peak records.
 hipError_t launch_windows(const ProbDev &P, int S, const double *phi, int *lo,
-                          int *hi, const int *perm, hipStream_t stream);
+                          int *hi, const int *perm, hipStream_t stream,
+                          float4 *psec = nullptr);
+// Per-(sample, peak) step of a2 for st: windows (windowed mode) and sec-law
+// records (sec law); nothing for a dense constant-width problem.
+hipError_t launch_peak_plan(const ProbDev &P, const StepDev &st,
+                            const double *phi, hipStream_t stream);
 hipError_t launch_plan(const ProbDev &P, const StepDev &st, const double *phi,
                        hipStream_t stream);
 hipError_t launch_fused(const ProbDev &P, const StepDev &st, bool grad,
@@ -56,9 +63,11 @@ struct StepShape {
     int ntiles, K, T, S, N;
     int D;          // latent types per phase (4, or 5 with asymmetry)
     bool dense;     // cutoff 0: the adjoint keeps per-tile partial sums
+    bool sec;       // sec width law: per-(sample, peak) records
 };
 inline StepShape step_shape(const ProbDev &P, int S) {
-    return StepShape{P.ntiles, P.K, P.T, S, P.N, P.D, P.cutoff == 0.0};
+    return StepShape{P.ntiles, P.K, P.T, S, P.N, P.D, P.cutoff == 0.0,
+                     P.sec != 0};
 }
 // Bytes of per-step device state, laid out by carve_step.
 size_t step_bytes(const StepShape &sh);

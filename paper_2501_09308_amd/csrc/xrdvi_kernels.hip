@@ -58,46 +58,49 @@ __global__ void k_phi_consts(ProbDev P, int S, const double *__restrict__ phi,
 }
 
 // a2: one thread per (sample, peak).  perm != NULL writes the caller's
-// peak order.
+// peak order; psec != NULL also writes the sec-law peak records.
+template <bool SEC>
 __global__ void k_windows(ProbDev P, int S, const double *__restrict__ phi,
-                          int *lo, int *hi, const int *__restrict__ perm) {
+                          int *lo, int *hi, const int *__restrict__ perm,
+                          float4 *psec) {
     const size_t n = (size_t)S * P.T;
     for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
          g += (size_t)gridDim.x * blockDim.x)
-        windows_elem(P, phi, lo, hi, perm, g);
+        windows_elem<SEC>(P, phi, lo, hi, perm, g, psec);
 }
 
 // a2 (cont.): peak ranges of every (sample, tile, phase).
+template <bool SEC>
 __global__ void k_plan(ProbDev P, StepDev st, const double *__restrict__ phi) {
     const size_t n = (size_t)st.S * P.ntiles * P.K;
     for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
          g += (size_t)gridDim.x * blockDim.x)
-        plan_elem(P, st, phi, g);
+        plan_elem<SEC>(P, st, phi, g);
 }
 
 // a3 + a4 (+ a6): grid (ntiles, S), kBlock threads.
-template <bool WIN, bool GRAD, bool ASYM>
+template <bool WIN, bool GRAD, bool ASYM, bool SEC>
 __global__ __launch_bounds__(kBlock) void k_fused(ProbDev P, StepDev st,
                                                   float *f_out) {
     __shared__ FusedSmem sm;
-    fused_tile<WIN, GRAD, ASYM>(P, st, blockIdx.x, blockIdx.y, f_out, sm);
+    fused_tile<WIN, GRAD, ASYM, SEC>(P, st, blockIdx.x, blockIdx.y, f_out, sm);
 }
 
 // a3 + a4 (windowed): forward tile with LDS-staged peak lists; grid
 // (ntiles, S), kBlock threads.
-template <bool ASYM>
+template <bool ASYM, bool SEC>
 __global__ __launch_bounds__(kBlock) void k_win(ProbDev P, StepDev st,
                                                 float *f_out) {
-    __shared__ WinSmem sm;
-    win_tile<ASYM>(P, st, blockIdx.x, blockIdx.y, f_out, sm);
+    __shared__ WinSmem<SEC> sm;
+    win_tile<ASYM, SEC>(P, st, blockIdx.x, blockIdx.y, f_out, sm);
 }
 
 // a6 (windowed): peak-major adjoint, one block per (sample, phase);
 // grid (K, S), kBlock threads.
-template <bool ASYM>
+template <bool ASYM, bool SEC>
 __global__ __launch_bounds__(kBlock) void k_adjoint_win(ProbDev P, StepDev st) {
     __shared__ double red[kWaves][12];
-    adjoint_phase<ASYM>(P, st, blockIdx.y, blockIdx.x, red);
+    adjoint_phase<ASYM, SEC>(P, st, blockIdx.y, blockIdx.x, red);
 }
 
 // a5: one block of 1024 threads.
@@ -161,13 +164,26 @@ hipError_t launch_phi_consts(const ProbDev &P, int S, const double *phi,
 }
 
 hipError_t launch_windows(const ProbDev &P, int S, const double *phi, int *lo,
-                          int *hi, const int *perm, hipStream_t stream) {
+                          int *hi, const int *perm, hipStream_t stream,
+                          float4 *psec) {
     const size_t n = (size_t)S * P.T;
     if (n == 0) return hipSuccess;
     size_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    k_windows<<<(unsigned)blocks, 256, 0, stream>>>(P, S, phi, lo, hi, perm);
+    if (P.sec)
+        k_windows<true><<<(unsigned)blocks, 256, 0, stream>>>(P, S, phi, lo, hi,
+                                                              perm, psec);
+    else
+        k_windows<false><<<(unsigned)blocks, 256, 0, stream>>>(P, S, phi, lo, hi,
+                                                               perm, nullptr);
     return hipGetLastError();
+}
+
+hipError_t launch_peak_plan(const ProbDev &P, const StepDev &st,
+                            const double *phi, hipStream_t stream) {
+    if (P.cutoff == 0.0 && !P.sec) return hipSuccess;
+    return launch_windows(P, st.S, phi, P.cutoff > 0.0 ? st.lo : nullptr,
+                          st.hi, nullptr, stream, P.sec ? st.psec : nullptr);
 }
 
 hipError_t launch_plan(const ProbDev &P, const StepDev &st, const double *phi,
@@ -175,37 +191,43 @@ hipError_t launch_plan(const ProbDev &P, const StepDev &st, const double *phi,
     const size_t n = (size_t)st.S * P.ntiles * P.K;
     size_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    k_plan<<<(unsigned)blocks, 256, 0, stream>>>(P, st, phi);
+    if (P.sec) k_plan<true><<<(unsigned)blocks, 256, 0, stream>>>(P, st, phi);
+    else k_plan<false><<<(unsigned)blocks, 256, 0, stream>>>(P, st, phi);
     return hipGetLastError();
 }
 
 // Dense: one fused forward + adjoint launch.  Windowed: the forward writes
 // the residual, the peak-major adjoint follows when `grad` is set.
-template <bool ASYM>
+template <bool ASYM, bool SEC>
 static void launch_fused_t(const ProbDev &P, const StepDev &st, bool grad,
                            float *f_out, hipStream_t stream) {
     dim3 g(P.ntiles, st.S);
     if (P.cutoff > 0.0) {
         StepDev sf = st;
         if (!grad) sf.rres = nullptr;
-        if (P.K >= kWinStageK) k_win<ASYM><<<g, kBlock, 0, stream>>>(P, sf, f_out);
-        else k_fused<true, false, ASYM><<<g, kBlock, 0, stream>>>(P, sf, f_out);
+        if (P.K >= kWinStageK) k_win<ASYM, SEC><<<g, kBlock, 0, stream>>>(P, sf, f_out);
+        else k_fused<true, false, ASYM, SEC><<<g, kBlock, 0, stream>>>(P, sf, f_out);
         if (grad) {
             dim3 ga(P.K, st.S);
-            k_adjoint_win<ASYM><<<ga, kBlock, 0, stream>>>(P, st);
+            k_adjoint_win<ASYM, SEC><<<ga, kBlock, 0, stream>>>(P, st);
         }
     } else {
         StepDev sd = st;
         sd.rres = nullptr;      // dense: the residual stays in LDS
-        if (grad) k_fused<false, true, ASYM><<<g, kBlock, 0, stream>>>(P, sd, f_out);
-        else k_fused<false, false, ASYM><<<g, kBlock, 0, stream>>>(P, sd, f_out);
+        if (grad) k_fused<false, true, ASYM, SEC><<<g, kBlock, 0, stream>>>(P, sd, f_out);
+        else k_fused<false, false, ASYM, SEC><<<g, kBlock, 0, stream>>>(P, sd, f_out);
     }
 }
 
 hipError_t launch_fused(const ProbDev &P, const StepDev &st, bool grad,
                         float *f_out, hipStream_t stream) {
-    if (P.D == 5) launch_fused_t<true>(P, st, grad, f_out, stream);
-    else launch_fused_t<false>(P, st, grad, f_out, stream);
+    if (P.D == 5) {
+        if (P.sec) launch_fused_t<true, true>(P, st, grad, f_out, stream);
+        else launch_fused_t<true, false>(P, st, grad, f_out, stream);
+    } else {
+        if (P.sec) launch_fused_t<false, true>(P, st, grad, f_out, stream);
+        else launch_fused_t<false, false>(P, st, grad, f_out, stream);
+    }
     return hipGetLastError();
 }
 
@@ -247,8 +269,7 @@ hipError_t launch_logpost(const ProbDev &P, const StepDev &st,
                           const double *zeros, const double *z, double *logp,
                           double *gz, hipStream_t stream) {
     hipError_t e = launch_sample(P, st, zeros, zeros, z, 0, 0, stream);
-    if (e == hipSuccess && P.cutoff > 0.0)
-        e = launch_windows(P, st.S, st.phi, st.lo, st.hi, nullptr, stream);
+    if (e == hipSuccess) e = launch_peak_plan(P, st, st.phi, stream);
     if (e == hipSuccess) e = launch_plan(P, st, st.phi, stream);
     if (e == hipSuccess) e = launch_fused(P, st, gz != nullptr, nullptr, stream);
     if (e == hipSuccess)

@@ -87,20 +87,39 @@ __device__ inline void sample_block(const ProbDev &P, const StepDev &st,
 }
 
 // ---- a2: window plan element g = s * T + j ---------------------------------
+// lo/hi: the peak's grid window (windowed mode; NULL skips it).  SEC (sec
+// width law): psec (NULL skips it) receives the peak's record
+// (c, I c, tan(theta) (pi/360) w, 0) with c = |cos theta|, theta = rho / 2,
+// in sorted peak order.  The
+// constant-width kernels are a separate instantiation, so they keep the
+// register budget of the window search alone.
+template <bool SEC>
 __device__ inline void windows_elem(const ProbDev &P, const double *phi,
                                     int *lo, int *hi, const int *perm,
-                                    size_t g) {
+                                    size_t g, float4 *psec) {
+#pragma clang fp contract(off)
     const int s = (int)(g / P.T), j = (int)(g % P.T);
     const int k = P.phase[j];
     const double *ph = phi + (size_t)s * P.D * P.K;
-    const int2 wnd = window_of(P, P.pos[j], ph[P.K + k], ph[2 * P.K + k],
-                               P.D == 5 ? ph[4 * P.K + k] : 1.0);
-    const size_t o = (size_t)s * P.T + (perm ? perm[j] : j);
-    lo[o] = wnd.x;
-    hi[o] = wnd.y;
+    const double mu = ph[P.K + k], w = ph[2 * P.K + k];
+    if (lo) {
+        const int2 wnd = window_of<SEC>(P, P.pos[j], mu, w,
+                                   P.D == 5 ? ph[4 * P.K + k] : 1.0);
+        const size_t o = (size_t)s * P.T + (perm ? perm[j] : j);
+        lo[o] = wnd.x;
+        hi[o] = wnd.y;
+    }
+    if (SEC && psec) {
+        const double th = (P.pos[j] + mu) * kHalfDegRad;
+        const double c = fabs(cos(th));
+        psec[(size_t)s * P.T + j] =
+            make_float4((float)c, (float)((double)P.inten[j] * c),
+                        (float)(tan(th) * kHalfDegRad * w), 0.f);
+    }
 }
 
 // ---- a2 (cont.): range element g = (s * ntiles + t) * K + k ---------------
+template <bool SEC>
 __device__ inline void plan_elem(const ProbDev &P, const StepDev &st,
                                  const double *phi, size_t g) {
     const int k = (int)(g % P.K);
@@ -108,10 +127,10 @@ __device__ inline void plan_elem(const ProbDev &P, const StepDev &st,
     const int t = (int)(st_idx % P.ntiles), s = (int)(st_idx / P.ntiles);
     if (P.D == 5) {
         int2 side;
-        st.rng[g] = tile_range(P, st, phi, s, t, k, &side);
+        st.rng[g] = tile_range<SEC>(P, st, phi, s, t, k, &side);
         st.rng2[g] = side;
     } else {
-        st.rng[g] = tile_range(P, st, phi, s, t, k, nullptr);
+        st.rng[g] = tile_range<SEC>(P, st, phi, s, t, k, nullptr);
     }
 }
 

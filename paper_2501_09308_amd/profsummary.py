@@ -5,8 +5,10 @@ profile notes.
 
 SPEC: {"out", "title", "cmd", "stats_csv", optional "fetch", "write",
 "cfetch", "cwrite" (FETCH_SIZE / WRITE_SIZE counter CSVs of the measured
-program and of the 1 GiB copy calibration), optional "sq" (SQ counter CSV),
-optional "record_kernel" and "extra"}.  With "record_kernel" the summary
+program and of the 1 GiB copy calibration), optional "sq" (SQ counter CSV,
+with SQ_WAVES, SQ_INSTS_VALU, SQ_WAVE_CYCLES and SQ_WAIT_ANY for the
+derived table), optional "flops" (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32
+counter CSV), optional "record_kernel" and "extra"}.  With "record_kernel" the summary
 ends with a traffic record: the calibrated HBM bytes per dispatch of that
 kernel and a hash of the kernel sources, which the benchmark reports as the
 kernel's measured traffic while the sources are unchanged.
@@ -69,7 +71,7 @@ def short(name: str) -> str:
 
 
 def summarize(out, title, cmd, stats_csv, fetch=None, write=None, cfetch=None,
-              cwrite=None, sq=None, record_kernel=None, extra=""):
+              cwrite=None, sq=None, flops=None, record_kernel=None, extra=""):
     L = [f"# {title}", "", "Commands (run from the repository root on the GPU box):",
          "", "```", cmd, "```", "",
          "| kernel | calls | avg us | min us | max us | % time |",
@@ -107,6 +109,37 @@ def summarize(out, title, cmd, stats_csv, fetch=None, write=None, cfetch=None,
         for k in names:
             L.append(f"| `{short(k)}` | " + " | ".join(
                 f"{c[(k, n)][1]:.4g}" if (k, n) in c else "" for n in cols) + " |")
+    avg_us = {short(n): a for n, _, a, _, _, _ in _stats(stats_csv)}
+    if flops:
+        c = _counters(flops)
+        L += ["", "Counter-measured FP32 VALU work (flops = 64 lanes x (ADD + MUL "
+              "+ 2 FMA + TRANS)):", "",
+              "| kernel | ADD | MUL | FMA | TRANS | executed GFLOP / dispatch | "
+              "avg us | executed TFLOP/s |", "|---|---|---|---|---|---|---|---|"]
+        for k in sorted({k for k, _ in c if "xrdvi" in k}):
+            v = {n: c.get((k, f"SQ_INSTS_VALU_{n}_F32"), (0, 0.0))[1]
+                 for n in ("ADD", "MUL", "FMA", "TRANS")}
+            if v["FMA"] + v["ADD"] + v["MUL"] < 1e5:
+                continue
+            gf = 64 * (v["ADD"] + v["MUL"] + 2 * v["FMA"] + v["TRANS"]) / 1e9
+            us = avg_us.get(short(k), float("nan"))
+            L.append(f"| `{short(k)}` | {v['ADD']:.3e} | {v['MUL']:.3e} | "
+                     f"{v['FMA']:.3e} | {v['TRANS']:.3e} | {gf:.2f} | {us:.1f} | "
+                     f"{gf / (us * 1e-6) / 1e3:.1f} |")
+    if sq:
+        c = _counters(sq)
+        rows = []
+        for k in sorted({k for k, _ in c if "xrdvi" in k}):
+            g = lambda n: c.get((k, n), (0, 0.0))[1]  # noqa: E731
+            if g("SQ_WAVES") > 0 and g("SQ_WAVE_CYCLES") > 0:
+                rows.append(f"| `{short(k)}` | {g('SQ_WAVES'):.0f} | "
+                            f"{g('SQ_INSTS_VALU') / g('SQ_WAVES'):.0f} | "
+                            f"{g('SQ_WAIT_ANY') / g('SQ_WAVE_CYCLES'):.2f} |")
+        if rows:
+            L += ["", "Fraction of wave-cycles spent waiting (SQ_WAIT_ANY / "
+                  "SQ_WAVE_CYCLES) and VALU instructions per wave:", "",
+                  "| kernel | waves | VALU / wave | waiting |", "|---|---|---|---|"]
+            L += rows
     if extra:
         L += ["", extra]
     if record is not None:

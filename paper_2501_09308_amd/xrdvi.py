@@ -46,7 +46,7 @@ class ProblemDesc(C.Structure):
                 ("peak_pos", C.POINTER(C.c_double)),
                 ("peak_int", C.POINTER(C.c_double)),
                 ("cutoff", C.c_double), ("prior", Prior),
-                ("asymmetric", C.c_int32)]
+                ("asymmetric", C.c_int32), ("width_law", C.c_int32)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -173,8 +173,9 @@ def _dev_f64(t, shape, name):
 
 def make_desc(x, y, bg, peak_off, peak_pos, peak_int, cutoff=0.0,
               lambda_h=0.0, mu_sd=0.03, w_shape=3.0, w_rate=100.0,
-              asymmetric=False, alpha_mean=1.0, alpha_sd=0.2):
-    """Builds a ProblemDesc over host arrays; returns (desc, keepalive)."""
+              asymmetric=False, alpha_mean=1.0, alpha_sd=0.2, width_law=0):
+    """Builds a ProblemDesc over host arrays; returns (desc, keepalive).
+    width_law: 0 (FWHM w) or 1 / "sec" (FWHM w sec(rho / 2))."""
     arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, bg)]
     off = np.ascontiguousarray(peak_off, dtype=np.int32)
     pos = np.ascontiguousarray(peak_pos, dtype=np.float64)
@@ -191,6 +192,7 @@ def make_desc(x, y, bg, peak_off, peak_pos, peak_int, cutoff=0.0,
     d.cutoff = float(cutoff)
     d.prior = Prior(lambda_h, mu_sd, w_shape, w_rate, alpha_mean, alpha_sd)
     d.asymmetric = 1 if asymmetric else 0
+    d.width_law = 1 if width_law == "sec" else int(width_law or 0)
     return d, (arrs, off, pos, inten)
 
 
@@ -240,11 +242,12 @@ class Problem:
 
     def __init__(self, ctx: Context, x, y, bg, peak_off, peak_pos, peak_int,
                  cutoff=0.0, lambda_h=0.0, mu_sd=0.03, w_shape=3.0,
-                 w_rate=100.0, asymmetric=False, alpha_mean=1.0, alpha_sd=0.2):
+                 w_rate=100.0, asymmetric=False, alpha_mean=1.0, alpha_sd=0.2,
+                 width_law=0):
         self.ctx = ctx
         d, keep = make_desc(x, y, bg, peak_off, peak_pos, peak_int, cutoff,
                             lambda_h, mu_sd, w_shape, w_rate, asymmetric,
-                            alpha_mean, alpha_sd)
+                            alpha_mean, alpha_sd, width_law)
         h = _VP()
         _check(ctx.lib.xrdvi_problem_create(ctx.handle, C.byref(d), C.byref(h)))
         self.handle = h
@@ -254,6 +257,7 @@ class Problem:
         self.N, self.K, self.T, self.lambda_h = N.value, K.value, T.value, lam.value
         self.cutoff = float(cutoff)
         self.D = 5 if asymmetric else 4     # latent types per phase
+        self.width_law = d.width_law
 
     @classmethod
     def from_workload(cls, ctx, prob, y, **kw):

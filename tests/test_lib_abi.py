@@ -33,6 +33,16 @@ def _args(**over):
 def test_validate_accepts_good_problem():
     assert X.xrdvi_validate(**_args()) == 0
     assert X.xrdvi_validate(**_args(asymmetric=True)) == 0
+    assert X.xrdvi_validate(**_args(width_law="sec")) == 0
+    assert X.xrdvi_validate(**_args(asymmetric=True, width_law=1)) == 0
+
+
+def test_validate_rejects_unknown_width_law():
+    d, keep = X.make_desc(**_args())
+    d.width_law = 2
+    lib = X.load()
+    assert lib.xrdvi_validate(C.byref(d)) == X.XRDVI_EINVAL
+    assert b"width_law" in lib.xrdvi_last_error()
 
 
 def test_validate_rejects_unknown_asymmetry_flag():
@@ -58,6 +68,10 @@ def test_validate_rejects_unknown_asymmetry_flag():
     (lambda a: a.update(peak_pos=np.full_like(a["peak_pos"], np.nan)), "finite"),
     (lambda a: a.update(asymmetric=True, alpha_sd=0.0), "alpha_sd"),
     (lambda a: a.update(asymmetric=True, alpha_mean=np.inf), "alpha_mean"),
+    (lambda a: a.update(width_law=1, peak_pos=np.concatenate(
+        [[180.0], a["peak_pos"][1:]])), "inside (0, 180)"),
+    (lambda a: a.update(width_law=1, peak_pos=np.concatenate(
+        [[-1.0], a["peak_pos"][1:]])), "inside (0, 180)"),
 ])
 def test_validate_rejects(mutate, msg):
     a = _args()
