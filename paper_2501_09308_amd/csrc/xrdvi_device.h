@@ -1141,17 +1141,26 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
             span = max(span, len[q]);
         }
         for (int c = 0; c < span; c += kWave) {
-            float R[kAdjPeaks];
-            double d[kAdjPeaks];
+            float R[kAdjPeaks], rv[kAdjPeaks];
+            double d[kAdjPeaks], xv[kAdjPeaks];
             bool valid[kAdjPeaks];
 #pragma unroll
             for (int q = 0; q < kAdjPeaks; ++q) {
                 valid[q] = c + lane < len[q];
                 // lanes outside the window read point 0 (lo can be N for an
-                // empty window at the end of the grid)
+                // empty window at the end of the grid) and weigh it by 0 (the
+                // residual is finite); every lane loads
                 const int ii = valid[q] ? lo[q] + c + lane : 0;
-                R[q] = valid[q] ? rres[ii] * I[q] : 0.f;
-                d[q] = P.x[ii] - rho[q];
+                rv[q] = rres[ii];
+                xv[q] = P.x[ii];
+            }
+            // all 2 kAdjPeaks loads are issued before the first use, so one
+            // memory latency covers them
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < kAdjPeaks; ++q) {
+                R[q] = rv[q] * (valid[q] ? I[q] : 0.f);
+                d[q] = xv[q] - rho[q];
             }
 #pragma unroll
             for (int q = 0; q < kAdjPeaks; ++q) {
