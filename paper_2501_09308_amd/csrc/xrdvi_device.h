@@ -1024,10 +1024,11 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
 // rounded to FP32 (its sign picks the side of an asymmetric peak).  Six
 // sums (twelve: six per side) accumulate per lane over the wave's peaks,
 // are reduced over the wave, then over the waves in fixed order.
-// SEC: iw2 and iw2r carry the peak's c, and wl / wh are the mu-sum weights
-// of the two sides (see SecW).
+// R = 0 for lanes outside the window (their terms vanish).  SEC: iw2 and
+// iw2r carry the peak's c, and wl / wh are the mu-sum weights of the two
+// sides (see SecW).
 template <bool ASYM, bool SEC>
-__device__ __forceinline__ void adj_point(bool valid, float R, double d,
+__device__ __forceinline__ void adj_point(float R, double d,
                                           float iw2, float iw2r, float c,
                                           const SecW &wl, const SecW &wh,
                                           float (&acc)[ASYM ? 12 : 6]) {
@@ -1037,33 +1038,28 @@ __device__ __forceinline__ void adj_point(bool valid, float R, double d,
     const float l = rcp_f32(tt);
     const float Rl = R * l;
     const float Rll = Rl * l;
-    float Re = 0.f, Req = 0.f;
-    const bool gauss = __builtin_expect(__any(valid && tt < 81.0f), 0);
-    if (gauss) {
-        Re = R * exp2_f32(1.0f - tt);
-        Req = Re * q2;
-    }
+    // the Gaussian is evaluated at every point of the window: testing for
+    // the points where it matters costs more than the exp2 it would save
+    // (beyond 8 FWHM, 2^(1 - tt) underflows to 0)
+    const float Re = R * exp2_f32(1.0f - tt);
+    const float Req = Re * q2;
     float m1L, m1G = 0.f;
     if (SEC) {
         const float kL = up ? wh.kL : wl.kL;
+        const float bG = up ? wh.bG : wl.bG;
+        const float gG = up ? wh.gG : wl.gG;
         m1L = fmaf(Rll, fmaf(c, q2, -2.f * kL), Rl * kL);
-        if (gauss) {
-            const float bG = up ? wh.bG : wl.bG;
-            const float gG = up ? wh.gG : wl.gG;
-            m1G = Re * fmaf(c, q2, fmaf(bG, tt, gG));
-        }
+        m1G = Re * fmaf(c, q2, fmaf(bG, tt, gG));
     }
     if (!ASYM) {
         acc[3] += Rl;
         acc[5] += Rll;
         if (SEC) acc[4] += m1L;
         else acc[4] = fmaf(Rll, q2, acc[4]);
-        if (gauss) {
-            acc[0] += Re;
-            if (SEC) acc[1] += m1G;
-            else acc[1] += Req;
-            acc[2] = fmaf(Req, q2, acc[2]);
-        }
+        acc[0] += Re;
+        if (SEC) acc[1] += m1G;
+        else acc[1] += Req;
+        acc[2] = fmaf(Req, q2, acc[2]);
     } else {
         if (!SEC) {
             m1L = Rll * q2;
@@ -1077,16 +1073,17 @@ __device__ __forceinline__ void adj_point(bool valid, float R, double d,
         acc[11] = fmaf(fu, Rll, acc[11]);
         acc[4] = fmaf(fd, m1L, acc[4]);
         acc[10] = fmaf(fu, m1L, acc[10]);
-        if (gauss) {
-            acc[0] = fmaf(fd, Re, acc[0]);
-            acc[6] = fmaf(fu, Re, acc[6]);
-            acc[1] = fmaf(fd, m1G, acc[1]);
-            acc[7] = fmaf(fu, m1G, acc[7]);
-            acc[2] = fmaf(fd, Reqq, acc[2]);
-            acc[8] = fmaf(fu, Reqq, acc[8]);
-        }
+        acc[0] = fmaf(fd, Re, acc[0]);
+        acc[6] = fmaf(fu, Re, acc[6]);
+        acc[1] = fmaf(fd, m1G, acc[1]);
+        acc[7] = fmaf(fu, m1G, acc[7]);
+        acc[2] = fmaf(fd, Reqq, acc[2]);
+        acc[8] = fmaf(fu, Reqq, acc[8]);
     }
 }
+
+// Word 3 of a gfx9-family buffer resource (32-bit data format, raw access).
+constexpr int kBufferFlags = 0x00020000;
 
 // Peaks a wave handles together: their scalar data and grid loads are issued
 // back to back, so one memory latency covers all of them.
@@ -1103,7 +1100,12 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
     const double mu = ph[K + k];
     const float iw2 = (float)(2.0 / ph[2 * K + k]);
     const float iw2r = ASYM ? asym_iw2(ph[2 * K + k], ph[4 * K + k]) : iw2;
-    const float *__restrict__ rres = st.rres + (size_t)s * P.N;
+    // bounded buffer views of the residual and the grid: 32-bit offsets,
+    // and reads past the end return 0
+    const __amdgpu_buffer_rsrc_t rres_rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(st.rres + (size_t)s * P.N), (short)0, P.N * 4, kBufferFlags);
+    const __amdgpu_buffer_rsrc_t x_rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)P.x, (short)0, P.N * 8, kBufferFlags);
     cptr<int> wlo = as_const(st.lo + (size_t)s * P.T);
     cptr<int> whi = as_const(st.hi + (size_t)s * P.T);
     cptr<double> pos = as_const(P.pos);
@@ -1147,12 +1149,15 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
 #pragma unroll
             for (int q = 0; q < kAdjPeaks; ++q) {
                 valid[q] = c + lane < len[q];
-                // lanes outside the window read point 0 (lo can be N for an
-                // empty window at the end of the grid) and weigh it by 0 (the
-                // residual is finite); every lane loads
-                const int ii = valid[q] ? lo[q] + c + lane : 0;
-                rv[q] = rres[ii];
-                xv[q] = P.x[ii];
+                // every lane loads; lanes outside the window weigh their
+                // point by 0, and points past the grid's end (a window ending
+                // at N, or lo = N for an empty one) read 0 from the bounded
+                // buffer loads
+                const int ii = lo[q] + c + lane;
+                rv[q] = __uint_as_float(
+                    __builtin_amdgcn_raw_buffer_load_b32(rres_rs, ii * 4, 0, 0));
+                xv[q] = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(x_rs, ii * 8, 0, 0));
             }
             // all 2 kAdjPeaks loads are issued before the first use, so one
             // memory latency covers them
@@ -1165,11 +1170,11 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
 #pragma unroll
             for (int q = 0; q < kAdjPeaks; ++q) {
                 if (SEC)
-                    adj_point<ASYM, true>(valid[q], R[q], d[q], iw2 * cq[q],
+                    adj_point<ASYM, true>(R[q], d[q], iw2 * cq[q],
                                           iw2r * cq[q], cq[q], SecW::of(tw[q]),
                                           SecW::of(tw[q] * ka), acc);
                 else
-                    adj_point<ASYM, false>(valid[q], R[q], d[q], iw2, iw2r, 1.f,
+                    adj_point<ASYM, false>(R[q], d[q], iw2, iw2r, 1.f,
                                            SecW{0.f, 0.f, 0.f}, SecW{0.f, 0.f, 0.f},
                                            acc);
             }
