@@ -133,6 +133,12 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
 // ---- Philox4x32-10 (Salmon et al., SC'11) + Box-Muller ------------------
 
 __device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0,
@@ -477,20 +483,6 @@ struct SegPeaks {
             return PeakRec{pt[j], sec[4 * j + 1], wlo[j], whi[j], sec[4 * j],
                            sec[4 * j + 2]};
         return PeakRec{pt[j], inten[j], wlo[j], whi[j], 1.f, 0.f};
-    }
-};
-
-// Peak records staged in LDS by the windowed tile (record j at pd[j + shift],
-// its sec-law c at pc[j + shift]).
-struct LdsPeaks {
-    const float4 *pd;
-    const float *pc;
-    int shift;
-    template <bool SEC>
-    __device__ __forceinline__ PeakRec rec(int j) const {
-        const float4 v = pd[j + shift];
-        return PeakRec{v.x, v.y, __float_as_int(v.z), __float_as_int(v.w),
-                       SEC ? pc[j + shift] : 1.f, 0.f};
     }
 };
 
@@ -849,49 +841,98 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
     }
 }
 
-// ---- windowed forward tile with LDS-staged peak lists ----------------------
+// ---- windowed forward tile: flat peak records in LDS ------------------------
 //
-// In windowed mode only a few peaks of each phase reach a tile, so fetching
-// each phase's range and then its peaks one dependent load at a time would
-// leave the waves waiting.  The block instead stages, 256 phases at a time,
-// every phase's range and constants and the records (position, intensity,
-// window) of all peaks that reach the tile in LDS, with all threads loading
-// in parallel; the waves then walk their phases from LDS.  A chunk whose
-// peaks exceed the staging capacity reads the overflow with scalar loads.
+// In windowed mode only one or two peaks of a phase reach a tile, so a loop
+// over phases would spend most of its time on per-phase set-up.  The block
+// instead stages, 256 phases at a time, one record per peak that reaches the
+// tile, holding all that its evaluation needs from its phase: the centre
+// relative to the tile, 2 c / (A w) below and above the centre (c = 1 without
+// the sec law; A = 1 below, alpha above), the Lorentzian and Gaussian
+// amplitudes I h r cL n / w and I h (1 - r) cG n / w (times c with the sec
+// law; the Gaussian one 0 where that term is negligible) and the window.
+// One thread per phase writes its phase's records, then the waves share the
+// flat list.  Phases whose records do not fit the staging space (they come
+// last in the chunk) are evaluated from global memory, phase by phase.
 constexpr int kWinChunk = kBlock;   // phases staged at a time (one per thread)
 constexpr int kWinPeaks = 1024;     // staged peak records per chunk
 // Staging pays for its barriers and prefix sum only with many phases per
-// tile: from this K on the windowed forward stages (12000 points, K = 300,
-// S = 32: 105 us instead of 135 us); below it each wave reads its phases with
-// scalar loads (3501 points, K = 50, S = 64: 22.6 us instead of 25.0 us).
+// tile: from this K on the windowed forward stages; below it each wave reads
+// its phases with scalar loads (fused_tile<true, false, ...>).
 constexpr int kWinStageK = 128;
 
-// SEC: the staged records also hold each peak's sec-law c (pc).
-template <bool SEC>
+// Second word of a staged record: the window, and for asymmetric peaks the
+// scale above the centre.
+template <bool ASYM>
+struct WinRec2 {
+    int lo, hi;
+    __device__ __forceinline__ float ahi(float alo) const { return alo; }
+};
+template <>
+struct WinRec2<true> {
+    int lo, hi;
+    float ah, pad;
+    __device__ __forceinline__ float ahi(float) const { return ah; }
+};
+
+template <bool ASYM>
 struct WinSmem {
-    int4 rg[kWinChunk];
-    float4 pk[kWinChunk];
-    int2 rg2[kWinChunk];
-    float pkr[kWinChunk];
-    int off[kWinChunk];
-    int wsum[kWaves];
-    float4 pd[kWinPeaks];
-    float pc[SEC ? kWinPeaks : 1];
+    float4 rec[kWinPeaks];          // (centre, 2c/(Aw) below, amp L, amp G)
+    WinRec2<ASYM> rec2[kWinPeaks];  // (lo, hi[, 2c/(alpha w)])
+    int wmax[kWaves], wcnt[kWaves];
     float sig[kWaves][kTile];
     float rres[kTile];
     double red[kWaves];
 };
 
 // Shared memory of a windowed tile of either kind.
-template <bool SEC>
+template <bool ASYM>
 union WinTileSmem {
     FusedSmem f;
-    WinSmem<SEC> w;
+    WinSmem<ASYM> w;
 };
+
+// The forward of one phase over the tile's points from global memory
+// (phases whose records did not fit the staging space).
+template <bool ASYM, bool SEC>
+__device__ void win_phase_global(const SegPeaks &sp, int4 r, int2 r2,
+                                 float4 cst, float iw2r,
+                                 const float (&u)[kPPL], const int (&idx)[kPPL],
+                                 float (&sig)[kPPL]) {
+    const int ja = __builtin_amdgcn_readfirstlane(r.x);
+    const int ga = __builtin_amdgcn_readfirstlane(r.y);
+    const int gb = __builtin_amdgcn_readfirstlane(r.z);
+    const int jb = __builtin_amdgcn_readfirstlane(r.w);
+    const float iw2 = cst.x, aG = cst.y, aL = cst.z, mu = cst.w;
+    float uq[kPPL], uqr[kPPL], accL[kPPL], accG[kPPL];
+#pragma unroll
+    for (int p = 0; p < kPPL; ++p) {
+        uq[p] = (u[p] - mu) * iw2;
+        uqr[p] = ASYM ? (u[p] - mu) * iw2r : uq[p];
+        accL[p] = 0.f;
+        accG[p] = 0.f;
+    }
+    if (ASYM) {
+        const int jr = __builtin_amdgcn_readfirstlane(r2.x);
+        const int jl = __builtin_amdgcn_readfirstlane(r2.y);
+        fwd_segment<true, false, kAbove, SEC>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
+        fwd_segment<true, true, kAbove, SEC>(sp, ga, jr, idx, uq, uqr, iw2, iw2r, accL, accG);
+        fwd_segment<true, true, kBoth, SEC>(sp, jr, jl, idx, uq, uqr, iw2, iw2r, accL, accG);
+        fwd_segment<true, true, kBelow, SEC>(sp, jl, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
+        fwd_segment<true, false, kBelow, SEC>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
+    } else {
+        fwd_segment<true, false, kBelow, SEC>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
+        fwd_segment<true, true, kBelow, SEC>(sp, ga, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
+        fwd_segment<true, false, kBelow, SEC>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
+    }
+#pragma unroll
+    for (int p = 0; p < kPPL; ++p)
+        sig[p] = fmaf(aL, accL[p], fmaf(aG, accG[p], sig[p]));
+}
 
 template <bool ASYM, bool SEC>
 __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
-                         float *f_out, WinSmem<SEC> &sm) {
+                         float *f_out, WinSmem<ASYM> &sm) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -904,13 +945,14 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
     const float *ptt = P.pt + (size_t)t * P.T;
     const int *wlo = st.lo + (size_t)s * P.T;
     const int *whi = st.hi + (size_t)s * P.T;
-    const float4 *psec = SEC ? st.psec + (size_t)s * P.T : nullptr;
+    const float *psec = SEC ? reinterpret_cast<const float *>(st.psec + (size_t)s * P.T)
+                            : nullptr;
     SegPeaks sp;
     sp.pt = as_const(ptt);
     sp.inten = as_const(P.inten);
     sp.wlo = as_const(wlo);
     sp.whi = as_const(whi);
-    sp.sec = as_const(reinterpret_cast<const float *>(psec));
+    sp.sec = as_const(psec);
 
     float u[kPPL];
     int idx[kPPL];
@@ -924,90 +966,103 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
 
     for (int c0 = 0; c0 < K; c0 += kWinChunk) {
         const int nk = min(kWinChunk, K - c0);
-        // ranges, constants and peak counts of this chunk's phases
-        int cnt = 0, ja = 0;
+        // this thread's phase: range, constants and peak count
+        int4 r = make_int4(0, 0, 0, 0);
+        int2 r2 = make_int2(0, 0);
+        float4 cst = make_float4(0.f, 0.f, 0.f, 0.f);
+        float iw2r = 0.f;
         if (tid < nk) {
-            const int4 r = rng[c0 + tid];
-            sm.rg[tid] = r;
-            sm.pk[tid] = pkv[c0 + tid];
+            r = rng[c0 + tid];
+            cst = pkv[c0 + tid];
             if (ASYM) {
-                sm.rg2[tid] = rng2[c0 + tid];
-                sm.pkr[tid] = pkrv[c0 + tid];
+                r2 = rng2[c0 + tid];
+                iw2r = pkrv[c0 + tid];
             }
-            ja = r.x;
-            cnt = r.w - r.x;
         }
-        // exclusive prefix of the counts over the block
+        const int cnt = r.w - r.x;
+        // inclusive prefix of the counts over the block
         int incl = cnt;
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
             const int v = __shfl_up(incl, o, kWave);
             if (lane >= o) incl += v;
         }
-        if (lane == kWave - 1) sm.wsum[wv] = incl;
+        if (lane == kWave - 1) sm.wcnt[wv] = incl;
         __syncthreads();
         int before = 0;
-        for (int w = 0; w < wv; ++w) before += sm.wsum[w];
-        const int excl = before + incl - cnt;
-        if (tid < nk) sm.off[tid] = excl;
-        for (int q = 0; q < cnt && excl + q < kWinPeaks; ++q) {
-            const int j = ja + q;
-            float I = P.inten[j];
-            if (SEC) {
-                const float4 v = psec[j];
-                I = v.y;
-                sm.pc[excl + q] = v.x;
+        for (int w = 0; w < wv; ++w) before += sm.wcnt[w];
+        incl += before;
+        const int excl = incl - cnt;
+        // records of the phases that fit (a prefix of the chunk: incl grows
+        // with the phase index)
+        const bool fits = tid < nk && incl <= kWinPeaks;
+        if (fits) {
+            const float iw2 = cst.x, aG = cst.y, aL = cst.z, mu = cst.w;
+            for (int q = 0; q < cnt; ++q) {
+                const int j = r.x + q;
+                float I = P.inten[j], c = 1.f;
+                if (SEC) {
+                    c = psec[4 * j];
+                    I = psec[4 * j + 1];
+                }
+                float alo = iw2 * c, ahi = alo;
+                if (ASYM) {
+                    const float ar = iw2r * c;
+                    if (j < r2.x) alo = ahi = ar;     // tile above the centre
+                    else if (j < r2.y) ahi = ar;      // tile straddles it
+                }
+                const bool gauss = j >= r.y && j < r.z;
+                sm.rec[excl + q] = make_float4(ptt[j] + mu, alo, I * aL,
+                                               gauss ? I * aG : 0.f);
+                WinRec2<ASYM> w2;
+                w2.lo = wlo[j];
+                w2.hi = whi[j];
+                if constexpr (ASYM) { w2.ah = ahi; w2.pad = 0.f; }
+                sm.rec2[excl + q] = w2;
             }
-            sm.pd[excl + q] = make_float4(ptt[j], I, __int_as_float(wlo[j]),
-                                          __int_as_float(whi[j]));
         }
+        // staged record count and number of fitting phases
+        const int nrec = wave_max_i32(fits ? incl : 0);
+        const int nfit = __builtin_popcountll(__ballot(fits));
+        __syncthreads();                       // prefix words read, records written
+        if (lane == 0) { sm.wmax[wv] = nrec; }
+        if (lane == 1) { sm.wcnt[wv] = nfit; }
         __syncthreads();
+        int n_flat = 0, n_fit = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            n_flat = max(n_flat, sm.wmax[w]);
+            n_fit += sm.wcnt[w];
+        }
+        n_flat = __builtin_amdgcn_readfirstlane(n_flat);
+        n_fit = __builtin_amdgcn_readfirstlane(n_fit);
 
-        for (int kl = wv; kl < nk; kl += kWaves) {
-            const int4 r = sm.rg[kl];
-            const int ja_k = __builtin_amdgcn_readfirstlane(r.x);
-            const int ga = __builtin_amdgcn_readfirstlane(r.y);
-            const int gb = __builtin_amdgcn_readfirstlane(r.z);
-            const int jb = __builtin_amdgcn_readfirstlane(r.w);
-            if (ja_k >= jb) continue;
-            const float4 c = sm.pk[kl];
-            const float iw2 = c.x, aG = c.y, aL = c.z, mu = c.w;
-            const float iw2r = ASYM ? sm.pkr[kl] : iw2;
-            int jr = gb, jl = gb;
-            if (ASYM) {
-                const int2 r2 = sm.rg2[kl];
-                jr = __builtin_amdgcn_readfirstlane(r2.x);
-                jl = __builtin_amdgcn_readfirstlane(r2.y);
-            }
-            float uq[kPPL], uqr[kPPL], accL[kPPL], accG[kPPL];
+        // the waves share the flat list
+#pragma unroll 2
+        for (int f = wv; f < n_flat; f += kWaves) {
+            const float4 a = sm.rec[f];
+            const WinRec2<ASYM> b = sm.rec2[f];
+            const float ah = b.ahi(a.y);
+            const bool g = __builtin_amdgcn_readfirstlane(__float_as_int(a.w)) != 0;
+            PeakMask<true> mk;
+            mk.lo = b.lo;
+            mk.hi = b.hi;
 #pragma unroll
             for (int p = 0; p < kPPL; ++p) {
-                uq[p] = (u[p] - mu) * iw2;
-                uqr[p] = ASYM ? (u[p] - mu) * iw2r : uq[p];
-                accL[p] = 0.f;
-                accG[p] = 0.f;
+                const float d = u[p] - a.x;
+                const float q2 = d * (ASYM ? (d >= 0.f ? ah : a.y) : a.y);
+                const float tt = mk.apply(idx[p], fmaf(q2, q2, 1.0f));
+                sig[p] = fmaf(a.z, rcp_f32(tt), sig[p]);
+                if (g) sig[p] = fmaf(a.w, exp2_f32(1.0f - tt), sig[p]);
             }
-            auto run = [&](const auto &pks) {
-                if (ASYM) {
-                    fwd_segment<true, false, kAbove, SEC>(pks, ja_k, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
-                    fwd_segment<true, true, kAbove, SEC>(pks, ga, jr, idx, uq, uqr, iw2, iw2r, accL, accG);
-                    fwd_segment<true, true, kBoth, SEC>(pks, jr, jl, idx, uq, uqr, iw2, iw2r, accL, accG);
-                    fwd_segment<true, true, kBelow, SEC>(pks, jl, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
-                    fwd_segment<true, false, kBelow, SEC>(pks, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
-                } else {
-                    fwd_segment<true, false, kBelow, SEC>(pks, ja_k, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
-                    fwd_segment<true, true, kBelow, SEC>(pks, ga, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
-                    fwd_segment<true, false, kBelow, SEC>(pks, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
-                }
-            };
-            const int base = __builtin_amdgcn_readfirstlane(sm.off[kl]);
-            if (base + (jb - ja_k) <= kWinPeaks) run(LdsPeaks{sm.pd, sm.pc, base - ja_k});
-            else run(sp);
-#pragma unroll
-            for (int p = 0; p < kPPL; ++p)
-                sig[p] = fmaf(aL, accL[p], fmaf(aG, accG[p], sig[p]));
         }
-        __syncthreads();
+        // phases that did not fit
+        for (int kl = n_fit + wv; kl < nk; kl += kWaves) {
+            const int k = c0 + kl;
+            win_phase_global<ASYM, SEC>(sp, rng[k], ASYM ? rng2[k] : make_int2(0, 0),
+                                        pkv[k], ASYM ? pkrv[k] : 0.f, u, idx, sig);
+        }
+        __syncthreads();                       // records consumed
     }
 
 #pragma unroll

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(ProbDev P, StepDev st,
 template <bool ASYM, bool SEC>
 __global__ __launch_bounds__(kBlock) void k_win(ProbDev P, StepDev st,
                                                 float *f_out) {
-    __shared__ WinSmem<SEC> sm;
+    __shared__ WinSmem<ASYM> sm;
     win_tile<ASYM, SEC>(P, st, blockIdx.x, blockIdx.y, f_out, sm);
 }
 
