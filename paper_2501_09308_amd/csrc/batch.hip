@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void kb_plan(const SlotDev *tab,
 template <bool WIN, bool ASYM, bool SEC>
 __global__ __launch_bounds__(kBlock) void kb_fused(const SlotDev *tab,
                                                    const SchedDev *sch) {
-    using Smem = typename std::conditional<WIN, WinTileSmem<ASYM>, FusedSmem>::type;
+    using Smem = typename std::conditional<WIN, WinSmem<ASYM>, FusedSmem>::type;
     __shared__ PrefixSmem ps;
     __shared__ Smem sm;
     load_prefix(sch, fused_kind(WIN, ASYM, SEC), ps);
@@ -136,8 +136,7 @@ __global__ __launch_bounds__(kBlock) void kb_fused(const SlotDev *tab,
         if (s >= d.st.S) continue;
         // windowed: forward only (the adjoint is peak-major); dense: fused
         if constexpr (WIN) {
-            if (d.P.K >= kWinStageK) win_tile<ASYM, SEC>(d.P, d.st, t, s, nullptr, sm.w);
-            else fused_tile<true, false, ASYM, SEC>(d.P, d.st, t, s, nullptr, sm.f);
+            win_tile<ASYM, SEC>(d.P, d.st, t, s, nullptr, sm);
         } else {
             fused_tile<false, true, ASYM, SEC>(d.P, d.st, t, s, nullptr, sm);
         }

@@ -450,7 +450,10 @@ struct FusedSmem {
 // For asymmetric peaks [ga, gb) splits further at jr and jl: the tile lies
 // above the centres of [ja, jr), straddles those of [jr, jl) and lies below
 // those of [jl, jb), so only [jr, jl) picks the width per point.
-// WIN: each lane is masked by the peak's exact window.
+// WIN: each lane is masked by the peak's exact window.  The step kernels use
+// this tile for the dense mode (WIN = false, every peak reaches every
+// point); the windowed forward is win_tile below, whose global-memory path
+// reuses the segment loops with WIN = true.
 template <bool WIN>
 struct PeakMask {
     int lo, hi;
@@ -856,10 +859,6 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
 // last in the chunk) are evaluated from global memory, phase by phase.
 constexpr int kWinChunk = kBlock;   // phases staged at a time (one per thread)
 constexpr int kWinPeaks = 1024;     // staged peak records per chunk
-// Staging pays for its barriers and prefix sum only with many phases per
-// tile: from this K on the windowed forward stages; below it each wave reads
-// its phases with scalar loads (fused_tile<true, false, ...>).
-constexpr int kWinStageK = 128;
 
 // Second word of a staged record: the window, and for asymmetric peaks the
 // scale above the centre.
@@ -883,13 +882,6 @@ struct WinSmem {
     float sig[kWaves][kTile];
     float rres[kTile];
     double red[kWaves];
-};
-
-// Shared memory of a windowed tile of either kind.
-template <bool ASYM>
-union WinTileSmem {
-    FusedSmem f;
-    WinSmem<ASYM> w;
 };
 
 // The forward of one phase over the tile's points from global memory

@@ -86,8 +86,8 @@ __global__ __launch_bounds__(kBlock) void k_fused(ProbDev P, StepDev st,
     fused_tile<WIN, GRAD, ASYM, SEC>(P, st, blockIdx.x, blockIdx.y, f_out, sm);
 }
 
-// a3 + a4 (windowed): forward tile with LDS-staged peak lists; grid
-// (ntiles, S), kBlock threads.
+// a3 + a4 (windowed): forward tile over its flat list of staged peak
+// records; grid (ntiles, S), kBlock threads.
 template <bool ASYM, bool SEC>
 __global__ __launch_bounds__(kBlock) void k_win(ProbDev P, StepDev st,
                                                 float *f_out) {
@@ -205,8 +205,7 @@ static void launch_fused_t(const ProbDev &P, const StepDev &st, bool grad,
     if (P.cutoff > 0.0) {
         StepDev sf = st;
         if (!grad) sf.rres = nullptr;
-        if (P.K >= kWinStageK) k_win<ASYM, SEC><<<g, kBlock, 0, stream>>>(P, sf, f_out);
-        else k_fused<true, false, ASYM, SEC><<<g, kBlock, 0, stream>>>(P, sf, f_out);
+        k_win<ASYM, SEC><<<g, kBlock, 0, stream>>>(P, sf, f_out);
         if (grad) {
             dim3 ga(P.K, st.S);
             k_adjoint_win<ASYM, SEC><<<ga, kBlock, 0, stream>>>(P, st);

@@ -96,4 +96,7 @@ def test_window_wider_than_the_grid_equals_dense():
                          dev(phi)).cpu().numpy()
     fw = X.xrdvi_profile(ctx, X.Problem.from_workload(ctx, prob, y, cutoff=1e6),
                          dev(phi)).cpu().numpy()
-    np.testing.assert_allclose(fw, f0, rtol=2e-6)
+    # the windowed forward forms x - rho as u - (p + mu) in FP32, the dense
+    # one through a fused multiply-add: each is within the profile bar of the
+    # oracle, and of each other
+    np.testing.assert_allclose(fw, f0, rtol=2e-5)
