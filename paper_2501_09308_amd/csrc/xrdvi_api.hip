@@ -102,7 +102,7 @@ StepDev carve_step(void *base, const StepShape &sh) {
 
 // Device layout of a prepared problem, in 256-byte aligned pieces.
 struct ProblemLayout {
-    size_t x, y, bg, lgy, u, off, ph, pos, inten, pt, perm, total;
+    size_t x, y, bg, lgy, u, off, ph, pos, inten, pt, perm, ptab, total;
 };
 
 static ProblemLayout problem_layout(int N, int K, int T) {
@@ -116,6 +116,7 @@ static ProblemLayout problem_layout(int N, int K, int T) {
     L.u = slot(4 * (size_t)nt * kTile); L.off = slot(4 * (size_t)(K + 1));
     L.ph = slot(4 * T1); L.pos = slot(8 * T1); L.inten = slot(4 * T1);
     L.pt = slot(4 * (size_t)nt * T1); L.perm = slot(4 * T1);
+    L.ptab = slot(4 * (size_t)K * (kTabBuckets + 1));
     L.total = o;
     return L;
 }
@@ -144,6 +145,20 @@ hipError_t upload_problem(const xrdvi_problem_desc &d, double lambda,
             inten[j] = (float)d.peak_int[perm[j]];
         }
     }
+    // position index per phase: first sorted peak at or after each of
+    // kTabBuckets + 1 equally spaced positions spanning the grid
+    const double tab_x0 = d.x[0];
+    const double tab_inv = N > 1 ? kTabBuckets / (d.x[N - 1] - d.x[0]) : 0.0;
+    std::vector<int> ptab((size_t)K * (kTabBuckets + 1));
+    for (int k = 0; k < K; ++k) {
+        const int a = d.peak_off[k], b = d.peak_off[k + 1];
+        int j = a;
+        for (int bb = 0; bb <= kTabBuckets; ++bb) {
+            const double v = tab_inv > 0.0 ? tab_x0 + bb / tab_inv : tab_x0;
+            while (j < b && pos[j] < v) ++j;
+            ptab[(size_t)k * (kTabBuckets + 1) + bb] = j;
+        }
+    }
     auto up = [&](size_t o, const void *src, size_t bytes) {
         return hipMemcpyAsync(base + o, src, bytes, hipMemcpyHostToDevice, stream);
     };
@@ -155,6 +170,7 @@ hipError_t upload_problem(const xrdvi_problem_desc &d, double lambda,
     if (e == hipSuccess) e = up(L.pos, pos.data(), 8 * (size_t)T1);
     if (e == hipSuccess) e = up(L.inten, inten.data(), 4 * (size_t)T1);
     if (e == hipSuccess) e = up(L.perm, perm.data(), 4 * (size_t)T1);
+    if (e == hipSuccess) e = up(L.ptab, ptab.data(), 4 * ptab.size());
     // pageable sources: complete the copies before the vectors go away
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return e;
@@ -187,6 +203,9 @@ hipError_t upload_problem(const xrdvi_problem_desc &d, double lambda,
     P.pos = (const double *)(base + L.pos);
     P.inten = (const float *)(base + L.inten);
     P.pt = (const float *)(base + L.pt);
+    P.ptab = (const int *)(base + L.ptab);
+    P.tab_x0 = tab_x0;
+    P.tab_inv = tab_inv;
     if (perm_out) *perm_out = (int *)(base + L.perm);
     return launch_prepare(P, (double *)(base + L.lgy), (float *)(base + L.u),
                           (float *)(base + L.pt), stream);

@@ -78,7 +78,14 @@ struct ProbDev {
     const double *pos;                // [T]
     const float *inten;               // [T]
     const float *pt;                  // [ntiles][T] p_j - xref_tile
+    // position index of each phase's sorted peaks: ptab[k][b] is the first
+    // peak j of phase k with pos[j] >= tab_x0 + b / tab_inv (b = 0 ..
+    // kTabBuckets), a starting guess for searches over positions
+    const int *ptab;
+    double tab_x0, tab_inv;
 };
+
+constexpr int kTabBuckets = 128;
 
 // Per-step state of one analysis with S samples.
 // Number of adjoint sums per (sample, phase): six, or six per side of the
@@ -260,15 +267,24 @@ __device__ __forceinline__ double peak_width(double rho, double w) {
 // for asymmetric peaks, alpha > 0; pass 1 otherwise), W the peak's full
 // width; each bound is one rounded FP64 operation (no contraction), as in
 // the model's definition.
+// The window's bounds a = rho - c W and b = rho + c W (rho + (c W) alpha for
+// asymmetric peaks).
+template <bool SEC>
+__device__ __forceinline__ double2 window_bounds(const ProbDev &P, double p,
+                                                 double mu, double w,
+                                                 double alpha) {
+#pragma clang fp contract(off)
+    const double rho = p + mu;
+    const double hw = P.cutoff * peak_width<SEC>(rho, w);
+    return make_double2(rho - hw, rho + (P.D == 5 ? hw * alpha : hw));
+}
+
 template <bool SEC>
 __device__ inline int2 window_of(const ProbDev &P, double p, double mu,
                                  double w, double alpha) {
-#pragma clang fp contract(off)
     if (P.cutoff == 0.0) return make_int2(0, P.N);
-    const double rho = p + mu;
-    const double hw = P.cutoff * peak_width<SEC>(rho, w);
-    const double a = rho - hw;
-    const double b = rho + (P.D == 5 ? hw * alpha : hw);
+    const double2 ab = window_bounds<SEC>(P, p, mu, w, alpha);
+    const double a = ab.x, b = ab.y;
     const int lo = lower_bound_x(P.x, P.N, P.x0, P.inv_dx, a);
     int hi = upper_bound_x(P.x, P.N, P.x0, P.inv_dx, b);
     if (hi < lo) hi = lo;
@@ -345,12 +361,39 @@ __device__ inline bool sec_monotone(double rf, double rl, double w, double R,
 
 // First j in [a, b) with pred(j) true (pred false then true over [a, b)).
 template <typename F>
-__device__ inline int first_true(int a, int b, F pred) {
+__host__ __device__ inline int first_true(int a, int b, F pred) {
     while (a < b) {
         const int mid = (a + b) >> 1;
         if (pred(mid)) b = mid; else a = mid + 1;
     }
     return a;
+}
+
+// The same search started from a guess g: a few steps from the guess
+// checking the predicate, then bisection of what remains.
+template <typename F>
+__host__ __device__ inline int first_true_from(int a, int b, int g, F pred) {
+    g = g < a ? a : (g > b ? b : g);
+    int lo = a, hi = b;
+    for (int step = 0; step < 4; ++step) {
+        if (g > lo && pred(g - 1)) {            // answer at or left of g - 1
+            hi = g - 1;
+            --g;
+        } else if (g < hi && !pred(g)) {        // answer right of g
+            lo = g + 1;
+            ++g;
+        } else {
+            return g;
+        }
+    }
+    return first_true(lo, hi, pred);
+}
+
+// Guess for the first peak of phase k whose position is >= v.
+__device__ __forceinline__ int tab_guess(const ProbDev &P, int k, double v) {
+    const double g = (v - P.tab_x0) * P.tab_inv;
+    const int b = !(g > 0.0) ? 0 : (g < (double)kTabBuckets ? (int)g : kTabBuckets);
+    return P.ptab[k * (kTabBuckets + 1) + b];
 }
 
 // Range entry of (sample s, tile t, phase k); phi: [S][D][K].  For
@@ -374,22 +417,39 @@ __device__ inline int4 tile_range(const ProbDev &P, const StepDev &st,
         win_mono = sec_monotone(rf, rl, w, P.cutoff, alpha);
         g_mono = sec_monotone(rf, rl, w, kGaussReach, alpha);
     }
+    const double xa = P.x[i0], xb = P.x[i1 - 1];
     int ja = a, jb = b;
     if (P.cutoff > 0.0 && win_mono) {
-        const int *lo = st.lo + (size_t)s * P.T;
-        const int *hi = st.hi + (size_t)s * P.T;
-        ja = first_greater(hi, a, b, i0);
-        jb = first_not_less(lo, ja, b, i1);
+        if (!SEC) {
+            // hi_j > i0 <=> x[i0] <= b_j and lo_j >= i1 <=> a_j > x[i1 - 1],
+            // with the window bounds (a_j, b_j) formed as the window step
+            // forms them; searched over the positions from a table guess
+            const double hw = P.cutoff * w;
+            const double hwu = P.D == 5 ? hw * alpha : hw;
+            ja = first_true_from(a, b, tab_guess(P, k, xa - mu - hwu), [&](int j) {
+                return xa <= window_bounds<false>(P, P.pos[j], mu, w, alpha).y;
+            });
+            jb = first_true_from(ja, b, tab_guess(P, k, xb - mu + hw), [&](int j) {
+                return window_bounds<false>(P, P.pos[j], mu, w, alpha).x > xb;
+            });
+        } else {
+            const int *lo = st.lo + (size_t)s * P.T;
+            const int *hi = st.hi + (size_t)s * P.T;
+            ja = first_greater(hi, a, b, i0);
+            jb = first_not_less(lo, ja, b, i1);
+        }
     }
     int ga = ja, gb = jb;
     if (!SEC) {
         const double reach = kGaussReach * w;       // below rho
         const double reach_hi = reach * alpha;      // above rho
         // Gaussian relevant: p + mu + reach_hi >= x[i0], p + mu - reach <= x[i1-1]
-        ga = first_not_less_d(P.pos, ja, jb, P.x[i0] - mu - reach_hi);
-        gb = first_greater_d(P.pos, ga, jb, P.x[i1 - 1] - mu + reach);
+        const double ka = xa - mu - reach_hi, kb = xb - mu + reach;
+        ga = first_true_from(ja, jb, tab_guess(P, k, ka),
+                             [&](int j) { return P.pos[j] >= ka; });
+        gb = first_true_from(ga, jb, tab_guess(P, k, kb),
+                             [&](int j) { return P.pos[j] > kb; });
     } else if (g_mono) {
-        const double xa = P.x[i0], xb = P.x[i1 - 1];
         ga = first_true(ja, jb, [&](int j) {
             const double rho = P.pos[j] + mu;
             return rho + kGaussReach * peak_width<SEC>(rho, w) * alpha >= xa;

@@ -1,5 +1,6 @@
 // Host check of the guessed-then-walked grid search against std::lower_bound
-// and std::upper_bound on uniform, jittered and strongly non-uniform grids.
+// and std::upper_bound on uniform, jittered and strongly non-uniform grids,
+// and of the guessed predicate search against a plain scan.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -45,6 +46,30 @@ int main() {
             checks += 2;
             if (lo != rlo || hi != rhi) {
                 if (bad < 5) std::printf("n=%d kind=%d v=%.17g: %d %d vs %d %d\n", n, kind, val, lo, hi, rlo, rhi);
+                ++bad;
+            }
+        }
+    }
+    // searches of a monotone predicate started from any guess (the tile
+    // plan's searches over peak positions) against a plain scan
+    for (int g = 0; g < 2000; ++g) {
+        const int n = (int)(U(rng) * 200);
+        std::vector<double> p(n);
+        double v = 0.0;
+        for (int j = 0; j < n; ++j) { v += (U(rng) < 0.1) ? 0.0 : U(rng); p[j] = v; }
+        const int a = n ? (int)(U(rng) * n) : 0;
+        const int b = a + (int)(U(rng) * (n - a + 1));
+        for (int q = 0; q < 20; ++q) {
+            const double key = -1.0 + (v + 2.0) * U(rng);
+            const int guess = -5 + (int)(U(rng) * (n + 10));
+            auto pred = [&](int j) { return p[j] >= key; };
+            int ref = a;
+            while (ref < b && !pred(ref)) ++ref;
+            const int got = xrdvi::first_true_from(a, b, guess, pred);
+            const int got0 = xrdvi::first_true(a, b, pred);
+            checks += 2;
+            if (got != ref || got0 != ref) {
+                if (bad < 5) std::printf("n=%d [%d,%d) guess=%d: %d %d vs %d\n", n, a, b, guess, got, got0, ref);
                 ++bad;
             }
         }
