@@ -62,7 +62,8 @@ inline void batch_units(const ProbDev &P, int S, int units[kKinds]) {
     units[kSample] = (int)(S * nkb);
     if (win || sec)
         units[sec ? kWindowsSec : kWindows] = (int)(((long long)S * P.T + 255) / 256);
-    units[sec ? kPlanSec : kPlan] = (int)(((long long)S * P.ntiles * P.K + 255) / 256);
+    if (!win)   // the windowed forward tile finds its own ranges
+        units[sec ? kPlanSec : kPlan] = (int)(((long long)S * P.ntiles * P.K + 255) / 256);
     units[fused_kind(win, asym, sec)] = P.ntiles * S;
     if (win) units[adjoint_kind(asym, sec)] = P.K * S;
     units[kElbo] = 1;

@@ -521,6 +521,7 @@ int xrdvi_profile(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     int rc = XRDVI_OK;
     if (!ensure_ws(ctx, step_bytes(step_shape(P, S)), &rc)) return rc;
     StepDev st = carve_step(ctx->ws, step_shape(P, S));
+    st.phi = const_cast<double *>(phi);   // read only: the kernels' samples
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(launch_phi_consts(P, S, phi, st.pk, st.pkr, s), "phi constants");
     HIP_TRY(launch_peak_plan(P, st, phi, s), "window plan");

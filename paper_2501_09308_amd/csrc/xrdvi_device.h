@@ -914,8 +914,8 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
 // the sec law; A = 1 below, alpha above), the Lorentzian and Gaussian
 // amplitudes I h r cL n / w and I h (1 - r) cG n / w (times c with the sec
 // law; the Gaussian one 0 where that term is negligible) and the window.
-// One thread per phase writes its phase's records, then the waves share the
-// flat list.  Phases whose records do not fit the staging space (they come
+// One thread per phase finds its phase's peak ranges over the tile and
+// writes its records, then the waves share the flat list.  Phases whose records do not fit the staging space (they come
 // last in the chunk) are evaluated from global memory, phase by phase.
 constexpr int kWinChunk = kBlock;   // phases staged at a time (one per thread)
 constexpr int kWinPeaks = 1024;     // staged peak records per chunk
@@ -990,8 +990,6 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int i0 = t * kTile;
     const int K = P.K;
-    const int4 *rng = st.rng + ((size_t)s * P.ntiles + t) * K;
-    const int2 *rng2 = ASYM ? st.rng2 + ((size_t)s * P.ntiles + t) * K : nullptr;
     const float4 *pkv = st.pk + (size_t)s * K;
     const float *pkrv = ASYM ? st.pkr + (size_t)s * K : nullptr;
     const float *ptt = P.pt + (size_t)t * P.T;
@@ -1018,18 +1016,16 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
 
     for (int c0 = 0; c0 < K; c0 += kWinChunk) {
         const int nk = min(kWinChunk, K - c0);
-        // this thread's phase: range, constants and peak count
+        // this thread's phase: its peak ranges over the tile (found here:
+        // the windowed forward is their only user), constants and count
         int4 r = make_int4(0, 0, 0, 0);
         int2 r2 = make_int2(0, 0);
         float4 cst = make_float4(0.f, 0.f, 0.f, 0.f);
         float iw2r = 0.f;
         if (tid < nk) {
-            r = rng[c0 + tid];
             cst = pkv[c0 + tid];
-            if (ASYM) {
-                r2 = rng2[c0 + tid];
-                iw2r = pkrv[c0 + tid];
-            }
+            if (ASYM) iw2r = pkrv[c0 + tid];
+            r = tile_range<SEC>(P, st, st.phi, s, t, c0 + tid, ASYM ? &r2 : nullptr);
         }
         const int cnt = r.w - r.x;
         // inclusive prefix of the counts over the block
@@ -1108,11 +1104,13 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
                 if (g) sig[p] = fmaf(a.w, exp2_f32(1.0f - tt), sig[p]);
             }
         }
-        // phases that did not fit
+        // phases that did not fit (every lane finds the same ranges)
         for (int kl = n_fit + wv; kl < nk; kl += kWaves) {
             const int k = c0 + kl;
-            win_phase_global<ASYM, SEC>(sp, rng[k], ASYM ? rng2[k] : make_int2(0, 0),
-                                        pkv[k], ASYM ? pkrv[k] : 0.f, u, idx, sig);
+            int2 rk2 = make_int2(0, 0);
+            const int4 rk = tile_range<SEC>(P, st, st.phi, s, t, k, ASYM ? &rk2 : nullptr);
+            win_phase_global<ASYM, SEC>(sp, rk, rk2, pkv[k], ASYM ? pkrv[k] : 0.f,
+                                        u, idx, sig);
         }
         __syncthreads();                       // records consumed
     }

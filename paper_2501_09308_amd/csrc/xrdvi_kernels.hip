@@ -186,8 +186,10 @@ hipError_t launch_peak_plan(const ProbDev &P, const StepDev &st,
                           st.hi, nullptr, stream, P.sec ? st.psec : nullptr);
 }
 
+// Dense mode only: the windowed forward tile finds its own ranges.
 hipError_t launch_plan(const ProbDev &P, const StepDev &st, const double *phi,
                        hipStream_t stream) {
+    if (P.cutoff > 0.0) return hipSuccess;
     const size_t n = (size_t)st.S * P.ntiles * P.K;
     size_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
