@@ -64,8 +64,9 @@ size_t step_bytes(const StepShape &sh) {
     b += align256(sizeof(double) * S * nt);         // llp
     b += align256(sh.dense ? sizeof(float) * NS * nt * K * S : 4);  // part
     b += align256(sizeof(double) * D);              // sd
-    b += align256(sizeof(int4) * S * nt * K);       // rng
-    b += align256(asym ? sizeof(int2) * S * nt * K : 4);  // rng2
+    // tile ranges: dense mode only (windowed tiles find their own)
+    b += align256(sh.dense ? sizeof(int4) * S * nt * K : 4);            // rng
+    b += align256(sh.dense && asym ? sizeof(int2) * S * nt * K : 4);    // rng2
     b += align256(sizeof(float) * S * (size_t)sh.N);  // rres
     b += align256(sizeof(double) * NS * K * S);     // pw
     b += align256(sh.sec ? sizeof(float4) * S * (size_t)std::max(sh.T, 1) : 4);  // psec
@@ -92,8 +93,8 @@ StepDev carve_step(void *base, const StepShape &sh) {
     st.llp = (double *)take(sizeof(double) * S * nt);
     st.part = (float *)take(sh.dense ? sizeof(float) * NS * nt * K * S : 4);
     st.sd = (double *)take(sizeof(double) * D);
-    st.rng = (int4 *)take(sizeof(int4) * S * nt * K);
-    st.rng2 = (int2 *)take(asym ? sizeof(int2) * S * nt * K : 4);
+    st.rng = (int4 *)take(sh.dense ? sizeof(int4) * S * nt * K : 4);
+    st.rng2 = (int2 *)take(sh.dense && asym ? sizeof(int2) * S * nt * K : 4);
     st.rres = (float *)take(sizeof(float) * S * (size_t)sh.N);
     st.pw = (double *)take(sizeof(double) * NS * K * S);
     st.psec = (float4 *)take(sh.sec ? sizeof(float4) * S * (size_t)std::max(sh.T, 1) : 4);

@@ -102,7 +102,7 @@ struct StepDev {
     double *lpj;      // [S][K] log prior + log|J|
     double *lpb;      // [S][ceil(K/64)] per-wave sums of lpj
     int *lo, *hi;     // [S][T] window plan (sorted peak order)
-    int4 *rng;        // [S][ntiles][K] peak ranges (ja, ga, gb, jb) of a
+    int4 *rng;        // dense mode: [S][ntiles][K] peak ranges (ja, ga, gb, jb) of a
                       // tile: [ja, jb) reach the tile, [ga, gb) need G
     int2 *rng2;       // [S][ntiles][K] (jr, jl) for D = 5: peaks before jr
                       // lie at or below every point of the tile, peaks from
