@@ -1131,46 +1131,38 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
 // are reduced over the wave, then over the waves in fixed order.
 // R = 0 for lanes outside the window (their terms vanish).  SEC: iw2 and
 // iw2r carry the peak's c, and wl / wh are the mu-sum weights of the two
-// sides (see SecW).
+// sides (see SecW).  The Lorentzian terms and the Gaussian terms are two
+// steps, so that a chunk of points where no Gaussian matters can skip the
+// second.
+struct AdjPt {
+    float R, q2, tt;
+    bool up;
+};
+
 template <bool ASYM, bool SEC>
-__device__ __forceinline__ void adj_point(float R, double d,
-                                          float iw2, float iw2r, float c,
-                                          const SecW &wl, const SecW &wh,
-                                          float (&acc)[ASYM ? 12 : 6]) {
+__device__ __forceinline__ AdjPt adj_point_L(float R, double d, float iw2,
+                                             float iw2r, float c,
+                                             const SecW &wl, const SecW &wh,
+                                             float (&acc)[ASYM ? 12 : 6]) {
     const bool up = ASYM && d >= 0.0;
     const float q2 = (float)d * (up ? iw2r : iw2);
     const float tt = fmaf(q2, q2, 1.0f);
     const float l = rcp_f32(tt);
     const float Rl = R * l;
     const float Rll = Rl * l;
-    // the Gaussian is evaluated at every point of the window: testing for
-    // the points where it matters costs more than the exp2 it would save
-    // (beyond 8 FWHM, 2^(1 - tt) underflows to 0)
-    const float Re = R * exp2_f32(1.0f - tt);
-    const float Req = Re * q2;
-    float m1L, m1G = 0.f;
+    float m1L;
     if (SEC) {
         const float kL = up ? wh.kL : wl.kL;
-        const float bG = up ? wh.bG : wl.bG;
-        const float gG = up ? wh.gG : wl.gG;
         m1L = fmaf(Rll, fmaf(c, q2, -2.f * kL), Rl * kL);
-        m1G = Re * fmaf(c, q2, fmaf(bG, tt, gG));
+    } else {
+        m1L = Rll * q2;
     }
     if (!ASYM) {
         acc[3] += Rl;
         acc[5] += Rll;
         if (SEC) acc[4] += m1L;
         else acc[4] = fmaf(Rll, q2, acc[4]);
-        acc[0] += Re;
-        if (SEC) acc[1] += m1G;
-        else acc[1] += Req;
-        acc[2] = fmaf(Req, q2, acc[2]);
     } else {
-        if (!SEC) {
-            m1L = Rll * q2;
-            m1G = Req;
-        }
-        const float Reqq = Req * q2;
         const float fu = up ? 1.f : 0.f, fd = 1.f - fu;
         acc[3] = fmaf(fd, Rl, acc[3]);
         acc[9] = fmaf(fu, Rl, acc[9]);
@@ -1178,6 +1170,32 @@ __device__ __forceinline__ void adj_point(float R, double d,
         acc[11] = fmaf(fu, Rll, acc[11]);
         acc[4] = fmaf(fd, m1L, acc[4]);
         acc[10] = fmaf(fu, m1L, acc[10]);
+    }
+    return AdjPt{R, q2, tt, up};
+}
+
+template <bool ASYM, bool SEC>
+__device__ __forceinline__ void adj_point_G(const AdjPt &pt, float c,
+                                            const SecW &wl, const SecW &wh,
+                                            float (&acc)[ASYM ? 12 : 6]) {
+    const float q2 = pt.q2, tt = pt.tt;
+    const float Re = pt.R * exp2_f32(1.0f - tt);
+    const float Req = Re * q2;
+    float m1G;
+    if (SEC) {
+        const float bG = pt.up ? wh.bG : wl.bG;
+        const float gG = pt.up ? wh.gG : wl.gG;
+        m1G = Re * fmaf(c, q2, fmaf(bG, tt, gG));
+    } else {
+        m1G = Req;
+    }
+    if (!ASYM) {
+        acc[0] += Re;
+        acc[1] += m1G;
+        acc[2] = fmaf(Req, q2, acc[2]);
+    } else {
+        const float Reqq = Req * q2;
+        const float fu = pt.up ? 1.f : 0.f, fd = 1.f - fu;
         acc[0] = fmaf(fd, Re, acc[0]);
         acc[6] = fmaf(fu, Re, acc[6]);
         acc[1] = fmaf(fd, m1G, acc[1]);
@@ -1186,6 +1204,10 @@ __device__ __forceinline__ void adj_point(float R, double d,
         acc[8] = fmaf(fu, Reqq, acc[8]);
     }
 }
+
+// The Gaussian matters where |x - rho| <= kGaussReach w (the forward's
+// rule): 1 + q2^2 <= 1 + (2 kGaussReach)^2.
+constexpr float kGaussTT = (float)(1.0 + 4.0 * kGaussReach * kGaussReach);
 
 // Word 3 of a gfx9-family buffer resource (32-bit data format, raw access).
 constexpr int kBufferFlags = 0x00020000;
@@ -1272,16 +1294,23 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
                 R[q] = rv[q] * (valid[q] ? I[q] : 0.f);
                 d[q] = xv[q] - rho[q];
             }
+            AdjPt pt[kAdjPeaks];
+            SecW wl[kAdjPeaks], wh[kAdjPeaks];
+            bool gauss = false;
 #pragma unroll
             for (int q = 0; q < kAdjPeaks; ++q) {
-                if (SEC)
-                    adj_point<ASYM, true>(R[q], d[q], iw2 * cq[q],
-                                          iw2r * cq[q], cq[q], SecW::of(tw[q]),
-                                          SecW::of(tw[q] * ka), acc);
-                else
-                    adj_point<ASYM, false>(R[q], d[q], iw2, iw2r, 1.f,
-                                           SecW{0.f, 0.f, 0.f}, SecW{0.f, 0.f, 0.f},
-                                           acc);
+                wl[q] = SecW::of(SEC ? tw[q] : 0.f);
+                wh[q] = SecW::of(SEC ? tw[q] * ka : 0.f);
+                pt[q] = adj_point_L<ASYM, SEC>(R[q], d[q], iw2 * cq[q], iw2r * cq[q],
+                                               cq[q], wl[q], wh[q], acc);
+                // (points outside the window lie beyond 8 FWHM: no effect)
+                gauss = gauss | (pt[q].tt <= kGaussTT);
+            }
+            // one wave-uniform branch over the four peaks' Gaussian terms
+            if (__builtin_amdgcn_readfirstlane(__any(gauss))) {
+#pragma unroll
+                for (int q = 0; q < kAdjPeaks; ++q)
+                    adj_point_G<ASYM, SEC>(pt[q], cq[q], wl[q], wh[q], acc);
             }
         }
     }
