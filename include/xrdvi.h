@@ -387,8 +387,9 @@ XRDVI_API int xrdvi_hmc(xrdvi_ctx *ctx, const xrdvi_problem *prob,
  * least squares (Eilers and Boelens 2005): starting from w = 1, n_iter
  * times solve (W + lambda D^T D) z = W y (D the second-difference
  * operator, W = diag(w)) and set w_i = p where y_i > z_i and 1 - p elsewhere;
- * the last z is the background.  FP64, one thread per spectrum, LDL^T of the
- * pentadiagonal system.
+ * the last z is the background.  FP64; one wave per spectrum solves the
+ * pentadiagonal system in parallel (blocks separated by 2-row separators,
+ * each factored as L D L^T, then the Schur complement on the separators).
  *   B, N      spectra and points per spectrum (>= 1)
  *   y         device double [B][N] counts
  *   lambda    smoothness (>= 0; e.g. 1e5 - 1e8 for 2-theta steps of 0.01 -
