@@ -13,14 +13,22 @@ from gpu_common import context, counts
 pytestmark = pytest.mark.gpu
 
 
+# grids from one partition block (N < 18) through two (18, 21), 64 blocks
+# of the minimum 8 rows (655) and long blocks (7001)
 @pytest.mark.parametrize("N,lam,p,n_iter", [(3501, 1e6, 0.01, 10),
                                             (1200, 1e5, 0.05, 4),
+                                            (7001, 1e7, 0.001, 6),
+                                            (655, 1e4, 0.01, 5),
+                                            (21, 100.0, 0.05, 3),
+                                            (18, 100.0, 0.05, 3),
+                                            (17, 50.0, 0.05, 3),
                                             (3, 10.0, 0.1, 3),
                                             (2, 1.0, 0.1, 2)])
 def test_background_matches_oracle(N, lam, p, n_iter):
     ys = []
     for b in range(3):
-        prob = W.make_problem("tiny", seed=900 + b, N=max(N, 3), K=4, M=10)
+        prob = W.make_problem("tiny", seed=900 + b, N=max(N, 3), K=4, M=10,
+                              step=min(0.02, 69.0 / max(N, 3)))
         ys.append(counts(prob, 950 + b)[:N])
     y = np.stack(ys)
     out = X.xrdvi_background(context(), torch.as_tensor(y, device="cuda"), lam, p,
