@@ -27,6 +27,8 @@ constexpr uint64_t kUniformKey = 0x9E3779B97F4A7C15ull;
 
 struct HmcDev {
     int C, n;                       // chains, coordinates per chain
+    int n_warmup;
+    int *iter;                      // current iteration (device counter)
     double *z, *z0, *g, *g0, *p;    // [C][n]
     double *logp, *logp0, *h0;      // [C]
     double *eps, *leps_bar, *hbar;  // [C] step, log averaged step, statistic
@@ -47,10 +49,10 @@ __device__ double block_sum(double v, double *red) {
 
 // Momentum draw, Hamiltonian at the start, first half step and position step.
 __global__ __launch_bounds__(kHmcBlock) void k_hmc_begin(HmcDev H,
-                                                         uint64_t seed,
-                                                         uint64_t iter) {
+                                                         uint64_t seed) {
 #pragma clang fp contract(off)
     __shared__ double red[kHmcBlock / kWave];
+    const uint64_t iter = (uint64_t)*H.iter;
     const int c = blockIdx.x;
     const size_t o = (size_t)c * H.n;
     const double eps = H.eps[c];
@@ -84,14 +86,18 @@ __global__ __launch_bounds__(kHmcBlock) void k_hmc_mid(HmcDev H) {
     }
 }
 
-// Last half step, Metropolis correction, step-size adaptation (warm > 0 is
-// the 1-based warm-up iteration) and the kept draw (d >= 0).
+// Last half step, Metropolis correction, step-size adaptation during
+// warm-up (frozen at the averaged step after the last warm-up iteration)
+// and the kept draw.
 __global__ __launch_bounds__(kHmcBlock) void k_hmc_end(
-    HmcDev H, uint64_t seed, uint64_t iter, int warm, int d, double *draws,
-    double *logp_draws) {
+    HmcDev H, uint64_t seed, double *draws, double *logp_draws) {
 #pragma clang fp contract(off)
     __shared__ double red[kHmcBlock / kWave];
     __shared__ int acc_s;
+    const int it = *H.iter;
+    const uint64_t iter = (uint64_t)it;
+    const int warm = it < H.n_warmup ? it + 1 : 0;     // 1-based warm-up step
+    const int d = it >= H.n_warmup ? it - H.n_warmup : -1;   // kept draw
     const int c = blockIdx.x;
     const size_t o = (size_t)c * H.n;
     const double eps = H.eps[c];
@@ -121,6 +127,7 @@ __global__ __launch_bounds__(kHmcBlock) void k_hmc_end(
             const double eta = pow(m, -H.kappa);
             H.leps_bar[c] = eta * leps + (1.0 - eta) * H.leps_bar[c];
             H.eps[c] = exp(leps);
+            if (warm == H.n_warmup) H.eps[c] = exp(H.leps_bar[c]);
         }
         if (d >= 0) {
             H.accepted[c] += acc;
@@ -138,15 +145,15 @@ __global__ __launch_bounds__(kHmcBlock) void k_hmc_end(
     }
 }
 
-// End of warm-up: every chain keeps its averaged step size.
-__global__ void k_hmc_freeze(HmcDev H) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < H.C) H.eps[c] = exp(H.leps_bar[c]);
+// Next iteration.
+__global__ void k_hmc_tick(HmcDev H) {
+    if (threadIdx.x == 0) *H.iter += 1;
 }
 
 // Initial per-chain state.
 __global__ void k_hmc_init(HmcDev H, double eps0) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c == 0) *H.iter = 0;
     if (c < H.C) {
         H.eps[c] = eps0;
         H.leps_bar[c] = 0.0;
@@ -192,7 +199,7 @@ extern "C" int xrdvi_hmc(xrdvi_ctx *ctx, const xrdvi_problem *prob,
         if (rc != XRDVI_OK) return rc;
         const size_t cn = (size_t)C * n;
         double *mem = nullptr;
-        if (hipMalloc(&mem, sizeof(double) * (4 * cn + 6 * (size_t)C) + sizeof(int) * C) !=
+        if (hipMalloc(&mem, sizeof(double) * (4 * cn + 6 * (size_t)C) + sizeof(int) * (C + 1)) !=
             hipSuccess) {
             xrdvi_tape_destroy(tape);
             return hfail(XRDVI_ENOMEM, "hmc: state allocation failed");
@@ -218,42 +225,61 @@ extern "C" int xrdvi_hmc(xrdvi_ctx *ctx, const xrdvi_problem *prob,
         H.t0 = 10.0;
         H.kappa = 0.75;
         H.delta = delta;
-        hipError_t e = hipSuccess;
-        k_hmc_init<<<(C + 255) / 256, 256, 0, s>>>(H, cfg->step_size);
-        e = hipGetLastError();
-        if (e == hipSuccess) rc = xrdvi_logpost(ctx, prob, C, H.z, H.logp, H.g, tape, stream);
+        H.n_warmup = cfg->n_warmup;
+        H.iter = H.accepted + C;
+        // The iterations run on a private stream (ordered after the caller's
+        // work) as replays of one captured iteration: begin, n_leapfrog
+        // gradients with the steps between them, end, and the counter tick.
+        hipStream_t hs = nullptr;
+        hipEvent_t ev = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t gexec = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&hs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(ev, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(hs, ev, 0);
+        if (e == hipSuccess) {
+            k_hmc_init<<<(C + 255) / 256, 256, 0, hs>>>(H, cfg->step_size);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) rc = xrdvi_logpost(ctx, prob, C, H.z, H.logp, H.g, tape, hs);
         const int total = cfg->n_warmup + cfg->n_draws;
-        for (int it = 0; rc == XRDVI_OK && e == hipSuccess && it < total; ++it) {
-            k_hmc_begin<<<C, kHmcBlock, 0, s>>>(H, cfg->seed, (uint64_t)it);
-            e = hipGetLastError();
-            for (int l = 1; rc == XRDVI_OK && e == hipSuccess && l <= cfg->n_leapfrog; ++l) {
-                rc = xrdvi_logpost(ctx, prob, C, H.z, H.logp, H.g, tape, stream);
-                if (rc == XRDVI_OK && l < cfg->n_leapfrog) {
-                    k_hmc_mid<<<C, kHmcBlock, 0, s>>>(H);
-                    e = hipGetLastError();
+        if (rc == XRDVI_OK && e == hipSuccess && total > 0) {
+            e = hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                k_hmc_begin<<<C, kHmcBlock, 0, hs>>>(H, cfg->seed);
+                for (int l = 1; rc == XRDVI_OK && l <= cfg->n_leapfrog; ++l) {
+                    rc = xrdvi_logpost(ctx, prob, C, H.z, H.logp, H.g, tape, hs);
+                    if (rc == XRDVI_OK && l < cfg->n_leapfrog)
+                        k_hmc_mid<<<C, kHmcBlock, 0, hs>>>(H);
                 }
+                k_hmc_end<<<C, kHmcBlock, 0, hs>>>(H, cfg->seed, draws, logp_draws);
+                k_hmc_tick<<<1, 1, 0, hs>>>(H);
+                const hipError_t el = hipGetLastError();
+                e = hipStreamEndCapture(hs, &graph);
+                if (e == hipSuccess) e = el;
             }
-            if (rc != XRDVI_OK || e != hipSuccess) break;
-            const int warm = it < cfg->n_warmup ? it + 1 : 0;
-            const int d = it >= cfg->n_warmup ? it - cfg->n_warmup : -1;
-            k_hmc_end<<<C, kHmcBlock, 0, s>>>(H, cfg->seed, (uint64_t)it, warm, d,
-                                             draws, logp_draws);
-            e = hipGetLastError();
-            if (e == hipSuccess && it + 1 == cfg->n_warmup) {
-                k_hmc_freeze<<<(C + 255) / 256, 256, 0, s>>>(H);
-                e = hipGetLastError();
-            }
+            if (e == hipSuccess && rc == XRDVI_OK)
+                e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+            for (int it = 0; rc == XRDVI_OK && e == hipSuccess && it < total; ++it)
+                e = hipGraphLaunch(gexec, hs);
         }
         std::vector<int> acc(C);
         std::vector<double> eps(C);
         if (rc == XRDVI_OK && e == hipSuccess)
             e = hipMemcpyAsync(acc.data(), H.accepted, sizeof(int) * C,
-                               hipMemcpyDeviceToHost, s);
+                               hipMemcpyDeviceToHost, hs);
         if (rc == XRDVI_OK && e == hipSuccess)
             e = hipMemcpyAsync(eps.data(), H.eps, sizeof(double) * C,
-                               hipMemcpyDeviceToHost, s);
-        const hipError_t es = hipStreamSynchronize(s);
-        if (e == hipSuccess) e = es;
+                               hipMemcpyDeviceToHost, hs);
+        if (hs) {
+            const hipError_t es = hipStreamSynchronize(hs);
+            if (e == hipSuccess) e = es;
+        }
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev) (void)hipEventDestroy(ev);
+        if (hs) (void)hipStreamDestroy(hs);
         (void)hipFree(mem);
         xrdvi_tape_destroy(tape);
         if (rc != XRDVI_OK) return rc;
