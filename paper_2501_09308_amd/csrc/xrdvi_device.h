@@ -495,15 +495,19 @@ __device__ __forceinline__ float in_vgpr(float v) {
     return v;
 }
 
-struct FusedSmem {
-    float sig[kWaves][kTile];
+// NW waves per block (kWaves, or more for grids too small to fill the GPU).
+template <int NW>
+struct FusedSmemT {
+    float sig[NW][kTile];
     float rres[kTile];
-    double red[kWaves];
+    double red[NW];
 };
+using FusedSmem = FusedSmemT<kWaves>;
 
 // ---- fused profile + likelihood + adjoint of one (tile, sample) ---------
 //
-// Four waves split the phases (k = wave, wave + 4, ...).  Every wave holds
+// NW waves (kWaves = 4 unless the grid is too small to fill the GPU) split
+// the phases (k = wave, wave + NW, ...).  Every wave holds
 // the same kTile points, kPPL per lane (point i0 + p*64 + lane).  Peak data
 // are wave-uniform (scalar loads).  Per phase the peaks run in segments:
 // [ja, ga) and [gb, jb) need only the Lorentzian, [ga, gb) both components.
@@ -746,6 +750,7 @@ __device__ __forceinline__ void store_sums(const Acc6 &a,
 // Point stage of a tile, after the waves' partial signals are in sig:
 // f = B + signal in FP64, the tile's Poisson log-likelihood (to st.llp) and
 // the residual y/f - 1 (to rres_lds, and to st.rres when it is set).
+template <int NW = kWaves>
 __device__ __forceinline__ void tile_points(const ProbDev &P, const StepDev &st,
                                             int t, int s, float *f_out,
                                             const float (*sig)[kTile],
@@ -754,13 +759,13 @@ __device__ __forceinline__ void tile_points(const ProbDev &P, const StepDev &st,
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int i0 = t * kTile;
     double ll = 0.0;
-    for (int q = threadIdx.x; q < kTile; q += kBlock) {
+    for (int q = threadIdx.x; q < kTile; q += NW * kWave) {
         const int i = i0 + q;
         float rr = 0.f;
         if (i < P.N) {
             double sg = 0.0;
 #pragma unroll
-            for (int w = 0; w < kWaves; ++w) sg += (double)sig[w][q];
+            for (int w = 0; w < NW; ++w) sg += (double)sig[w][q];
             const double f = P.bg[i] + sg;
             if (f_out) f_out[(size_t)s * P.N + i] = (float)f;
             const double y = P.y[i];
@@ -776,14 +781,14 @@ __device__ __forceinline__ void tile_points(const ProbDev &P, const StepDev &st,
     if (threadIdx.x == 0 && st.llp) {
         double tot = 0.0;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) tot += red[w];
+        for (int w = 0; w < NW; ++w) tot += red[w];
         st.llp[(size_t)s * P.ntiles + t] = tot;
     }
 }
 
-template <bool WIN, bool GRAD, bool ASYM, bool SEC>
+template <bool WIN, bool GRAD, bool ASYM, bool SEC, int NW = kWaves>
 __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
-                           float *f_out, FusedSmem &sm) {
+                           float *f_out, FusedSmemT<NW> &sm) {
     const int lane = threadIdx.x & (kWave - 1);
     // wave index as a wave-uniform (scalar) value: loops over phases and
     // peaks then run on the scalar unit and peak data use scalar loads
@@ -820,7 +825,7 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
 #pragma unroll
     for (int p = 0; p < kPPL; ++p) sig[p] = 0.f;
 
-    for (int k = wv; k < P.K; k += kWaves) {
+    for (int k = wv; k < P.K; k += NW) {
         const int ja = rg[4 * k], ga = rg[4 * k + 1], gb = rg[4 * k + 2],
                   jb = rg[4 * k + 3];
         if (ja >= jb) continue;
@@ -856,7 +861,7 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
     for (int p = 0; p < kPPL; ++p) sm.sig[wv][p * kWave + lane] = sig[p];
     __syncthreads();
 
-    tile_points(P, st, t, s, f_out, sm.sig, sm.rres, sm.red);
+    tile_points<NW>(P, st, t, s, f_out, sm.sig, sm.rres, sm.red);
     if (!GRAD) return;
 
     // ---------------- adjoint: recompute every peak value; the phase's sums
@@ -866,7 +871,7 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
 #pragma unroll
     for (int p = 0; p < kPPL; ++p) rres[p] = sm.rres[p * kWave + lane];
 
-    for (int k = wv; k < P.K; k += kWaves) {
+    for (int k = wv; k < P.K; k += NW) {
         float *dst = st.part + (((size_t)t * P.K + k) * st.S + s) * NS;
         const int ja = rg[4 * k], ga = rg[4 * k + 1], gb = rg[4 * k + 2],
                   jb = rg[4 * k + 3];

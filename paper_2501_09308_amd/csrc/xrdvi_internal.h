@@ -31,8 +31,11 @@ hipError_t launch_peak_plan(const ProbDev &P, const StepDev &st,
                             const double *phi, hipStream_t stream);
 hipError_t launch_plan(const ProbDev &P, const StepDev &st, const double *phi,
                        hipStream_t stream);
+// wide: dense tiles with more waves each (small grids; other summation
+// order of the partial signals, so not for results that must match across
+// paths bit for bit).
 hipError_t launch_fused(const ProbDev &P, const StepDev &st, bool grad,
-                        float *f_out, hipStream_t stream);
+                        float *f_out, hipStream_t stream, bool wide = false);
 // logp_out: per-sample log posterior density; gz_out: per-sample gradient
 // of it in z, [S][D K] (both optional).
 hipError_t launch_elbo(const ProbDev &P, const StepDev &st,

@@ -86,6 +86,17 @@ __global__ __launch_bounds__(kBlock) void k_fused(ProbDev P, StepDev st,
     fused_tile<WIN, GRAD, ASYM, SEC>(P, st, blockIdx.x, blockIdx.y, f_out, sm);
 }
 
+// Dense a3 + a4 + a6 with kWideWaves waves per tile, for grids of too few
+// (tile, sample) blocks to fill the GPU (the log-posterior path of
+// Hamiltonian Monte Carlo with a few chains); kWideWaves * 64 threads.
+constexpr int kWideWaves = 16;
+template <bool GRAD, bool ASYM, bool SEC>
+__global__ __launch_bounds__(kWideWaves * kWave) void k_fused_wide(ProbDev P, StepDev st,
+                                                                  float *f_out) {
+    __shared__ FusedSmemT<kWideWaves> sm;
+    fused_tile<false, GRAD, ASYM, SEC, kWideWaves>(P, st, blockIdx.x, blockIdx.y, f_out, sm);
+}
+
 // a3 + a4 (windowed): forward tile over its flat list of staged peak
 // records; grid (ntiles, S), kBlock threads.
 template <bool ASYM, bool SEC>
@@ -202,7 +213,7 @@ hipError_t launch_plan(const ProbDev &P, const StepDev &st, const double *phi,
 // the residual, the peak-major adjoint follows when `grad` is set.
 template <bool ASYM, bool SEC>
 static void launch_fused_t(const ProbDev &P, const StepDev &st, bool grad,
-                           float *f_out, hipStream_t stream) {
+                           float *f_out, hipStream_t stream, bool wide) {
     dim3 g(P.ntiles, st.S);
     if (P.cutoff > 0.0) {
         StepDev sf = st;
@@ -215,19 +226,26 @@ static void launch_fused_t(const ProbDev &P, const StepDev &st, bool grad,
     } else {
         StepDev sd = st;
         sd.rres = nullptr;      // dense: the residual stays in LDS
-        if (grad) k_fused<false, true, ASYM, SEC><<<g, kBlock, 0, stream>>>(P, sd, f_out);
-        else k_fused<false, false, ASYM, SEC><<<g, kBlock, 0, stream>>>(P, sd, f_out);
+        if (wide) {
+            const int nt = kWideWaves * kWave;
+            if (grad) k_fused_wide<true, ASYM, SEC><<<g, nt, 0, stream>>>(P, sd, f_out);
+            else k_fused_wide<false, ASYM, SEC><<<g, nt, 0, stream>>>(P, sd, f_out);
+        } else if (grad) {
+            k_fused<false, true, ASYM, SEC><<<g, kBlock, 0, stream>>>(P, sd, f_out);
+        } else {
+            k_fused<false, false, ASYM, SEC><<<g, kBlock, 0, stream>>>(P, sd, f_out);
+        }
     }
 }
 
 hipError_t launch_fused(const ProbDev &P, const StepDev &st, bool grad,
-                        float *f_out, hipStream_t stream) {
+                        float *f_out, hipStream_t stream, bool wide) {
     if (P.D == 5) {
-        if (P.sec) launch_fused_t<true, true>(P, st, grad, f_out, stream);
-        else launch_fused_t<true, false>(P, st, grad, f_out, stream);
+        if (P.sec) launch_fused_t<true, true>(P, st, grad, f_out, stream, wide);
+        else launch_fused_t<true, false>(P, st, grad, f_out, stream, wide);
     } else {
-        if (P.sec) launch_fused_t<false, true>(P, st, grad, f_out, stream);
-        else launch_fused_t<false, false>(P, st, grad, f_out, stream);
+        if (P.sec) launch_fused_t<false, true>(P, st, grad, f_out, stream, wide);
+        else launch_fused_t<false, false>(P, st, grad, f_out, stream, wide);
     }
     return hipGetLastError();
 }
@@ -272,7 +290,10 @@ hipError_t launch_logpost(const ProbDev &P, const StepDev &st,
     hipError_t e = launch_sample(P, st, zeros, zeros, z, 0, 0, stream);
     if (e == hipSuccess) e = launch_peak_plan(P, st, st.phi, stream);
     if (e == hipSuccess) e = launch_plan(P, st, st.phi, stream);
-    if (e == hipSuccess) e = launch_fused(P, st, gz != nullptr, nullptr, stream);
+    // a few chains give too few (tile, sample) blocks to fill the GPU: the
+    // dense tile then splits its phases over more waves
+    const bool wide = P.cutoff == 0.0 && (long long)P.ntiles * st.S < 4LL * 256;
+    if (e == hipSuccess) e = launch_fused(P, st, gz != nullptr, nullptr, stream, wide);
     if (e == hipSuccess)
         e = launch_elbo(P, st, zeros, nullptr, nullptr, stream, logp);
     if (e == hipSuccess && gz)
