@@ -22,14 +22,18 @@ UNIFORM_KEY = 0x9E3779B97F4A7C15
 LN_2PI = math.log(2.0 * math.pi)
 
 
-def logpost(prob, y, z, lam=0.0, asymmetric=False, **prior):
+def logpost(prob, y, z, lam=0.0, asymmetric=False, width_law=0, **prior):
     """ln p(Y|phi(z)) + ln p(phi(z)) + ln|J(z)| and its gradient in z, for
     one position z [D][K]: the ELBO estimate at zero noise and unit scale
-    (mean z) minus its entropy term D K (1 + ln 2 pi) / 2."""
+    (mean z) minus its entropy term D K (1 + ln 2 pi) / 2.  width_law
+    "sec" (or 1): the angle-dependent width (D taken from z)."""
     z = np.asarray(z, dtype=np.float64)
     zeros = np.zeros_like(z)
     eps = np.zeros((1,) + z.shape)
-    fn = O.elbo_asym if asymmetric else O.elbo
+    if width_law in (1, "sec"):
+        fn = O.elbo_sec
+    else:
+        fn = O.elbo_asym if asymmetric else O.elbo
     e, _, g, _ = fn(prob, y, z, zeros, eps, lam=lam, **prior)
     return e - 0.5 * z.size * (1.0 + LN_2PI), g
 

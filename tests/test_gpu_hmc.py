@@ -28,20 +28,23 @@ def _positions(prob, y, C, seed, D=4, spread=0.05):
     return base[None] + spread * rng.standard_normal((C, D, prob.K))
 
 
-@pytest.mark.parametrize("c,asym", [(0.0, False), (8.0, False), (0.0, True),
-                                    (3.0, True)])
-def test_logpost_and_gradient_match_oracle(c, asym):
+# dense cases run the 16-wave tile (16 tiles x 6 chains is a small grid)
+@pytest.mark.parametrize("c,asym,law", [(0.0, False, 0), (8.0, False, 0),
+                                        (0.0, True, 0), (3.0, True, 0),
+                                        (0.0, False, "sec"), (8.0, True, "sec")])
+def test_logpost_and_gradient_match_oracle(c, asym, law):
     prob, y = case("paper50", 801, N=2000, K=12, M=15)
     prob.cutoff = c
     ctx = context()
-    P = X.Problem.from_workload(ctx, prob, y, cutoff=c, asymmetric=asym)
+    P = X.Problem.from_workload(ctx, prob, y, cutoff=c, asymmetric=asym,
+                                width_law=law)
     C = 6
     z = _positions(prob, y, C, 802, D=P.D)
     tape = X.Tape(ctx, P, C)
     lp, g = X.xrdvi_logpost(ctx, P, tape, dev(z))
     lp, g = lp.cpu().numpy(), g.cpu().numpy()
     for s in range(C):
-        rl, rg = OH.logpost(prob, y, z[s], asymmetric=asym)
+        rl, rg = OH.logpost(prob, y, z[s], asymmetric=asym, width_law=law)
         assert abs(lp[s] - rl) <= 1e-6 * abs(rl)
         assert rel_l2(g[s], rg) <= 1e-4
 
