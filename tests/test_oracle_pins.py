@@ -420,3 +420,32 @@ def test_adam_first_step_is_signed_lr(orc):
     g = np.array([3.0, -0.01, 0.0])
     orc.adam(th, m1, m2, g, 1, lr=0.01)
     np.testing.assert_allclose(th, [1.01, -2.01, 0.5], rtol=1e-6)
+
+
+def test_gradient_central_differences_at_stress200_scale(orc):
+    # 200 phases x 60 peaks over 10-80 deg (the stress200 candidate set, on a
+    # 0.07 deg grid to keep the oracle fast), S = 2, dense: 32 random
+    # coordinates of (m, omega) against central differences, h = 1e-5
+    prob = W.make_problem("stress200", 3101, N=1001, step=0.07)
+    f = orc.profile(prob.x, prob.bg, prob.peak_off, prob.peak_pos,
+                    prob.peak_int, 0.0, prob.phi_true)[0]
+    y = W.poisson_counts(f, 3102)
+    lam = 1 / (y - prob.bg).max()
+    loc, ls = W.random_params(prob.K, 3103, (y - prob.bg).max(), spread=0.2)
+    eps = W.eps_draw(2, prob.K, 3104)
+    _, _, gl, gs = orc.elbo(prob, y, loc, ls, eps, lam=lam, c=0.0)
+    rng = np.random.default_rng(3105)
+    h = 1e-5
+    fd, an = [], []
+    for _ in range(32):
+        which, t, k = rng.integers(2), rng.integers(4), rng.integers(prob.K)
+        plus = [loc.copy(), ls.copy()]
+        minus = [loc.copy(), ls.copy()]
+        plus[which][t, k] += h
+        minus[which][t, k] -= h
+        ep = orc.elbo(prob, y, *plus, eps, lam=lam, c=0.0, grad=False)[0]
+        em = orc.elbo(prob, y, *minus, eps, lam=lam, c=0.0, grad=False)[0]
+        fd.append((ep - em) / (2 * h))
+        an.append((gl if which == 0 else gs)[t, k])
+    fd, an = np.array(fd), np.array(an)
+    np.testing.assert_allclose(an, fd, rtol=2e-6, atol=1e-6 * np.abs(an).max())
