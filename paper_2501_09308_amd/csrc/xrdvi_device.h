@@ -246,13 +246,108 @@ __host__ __device__ inline int grid_bound(const double *x, int n, double x0,
     return lo;
 }
 
-__device__ inline int lower_bound_x(const double *x, int n, double x0,
-                                    double inv_dx, double v) {
-    return grid_bound<false>(x, n, x0, inv_dx, v);
+
+// Batched searches.  A search from a good guess costs one round trip to
+// memory when the entries around the guess are loaded together: a probe
+// loads NP consecutive entries from j0 (several searches issue their probes
+// before any result is needed), and the answer is read off the probe when
+// it lies inside.  Otherwise the search moves a whole probe towards it (two
+// more probes at most) and bisects what remains.  Entries are read clamped
+// to [a, b - 1] (entry 0 when the range is empty), so every load stays in
+// bounds for any j0.
+template <int NP, typename T>
+struct Probe {
+    int j0;
+    T v[NP];
+};
+
+template <int NP, typename T>
+__host__ __device__ __forceinline__ Probe<NP, T> probe_at(const T *v, int a,
+                                                         int b, int j0) {
+    Probe<NP, T> p;
+    p.j0 = j0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const int j = j0 + i < a ? a : (j0 + i > b - 1 ? b - 1 : j0 + i);
+        p.v[i] = v[a < b ? j : 0];
+    }
+    return p;
 }
-__device__ inline int upper_bound_x(const double *x, int n, double x0,
-                                    double inv_dx, double v) {
-    return grid_bound<true>(x, n, x0, inv_dx, v);
+
+// The number of leading entries of a probe (loaded by probe_at with the
+// same a and b) whose predicate is false, pred false and then true over
+// [a, b): entries below a count as false and entries at or past b as true.
+// Evaluating every probe this way first leaves one integer per search live
+// instead of the probed values.
+template <int NP, typename T, typename F>
+__host__ __device__ __forceinline__ int probe_count(const Probe<NP, T> &p,
+                                                   int a, int b, F pred) {
+    int nf = 0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const int j = p.j0 + i;
+        nf += (j >= b || (j >= a && pred(p.v[i]))) ? 0 : 1;
+    }
+    return nf;
+}
+
+// First j in [a, b) with pred(v[j]) true, b if none, given the count nf of
+// a probe at j0: the answer j0 + nf when it lies inside the probe, otherwise
+// the search goes on by whole probes (two more at most), then bisects.
+template <int NP, typename T, typename F>
+__host__ __device__ inline int probe_settle(const T *v, int a, int b, int j0,
+                                            int nf, F pred) {
+    if (a >= b) return a;
+    int lo = a, hi = b;                     // the answer lies in [lo, hi]
+    for (int round = 0;; ++round) {
+        if (nf > 0 && nf < NP) return j0 + nf;
+        if (nf == 0) hi = j0 < hi ? j0 : hi;               // at or left of j0
+        else lo = j0 + NP > lo ? j0 + NP : lo;             // right of the probe
+        if (lo >= hi || round == 2) break;
+        j0 = nf == 0 ? (hi - NP > lo ? hi - NP : lo) : lo;
+        nf = probe_count(probe_at<NP>(v, a, b, j0), a, b, pred);
+    }
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (pred(v[mid])) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+template <int NP, typename T, typename F>
+__host__ __device__ inline int probe_result(const T *v, int a, int b,
+                                            const Probe<NP, T> &p, F pred) {
+    return probe_settle<NP>(v, a, b, p.j0, probe_count(p, a, b, pred), pred);
+}
+
+// Grid range [lo, hi) of the points with va <= x_i <= vb (lo = first i with
+// x[i] >= va, hi = first i with x[i] > vb; the comparisons of grid_bound,
+// so NaN gives 0), each bound from a two-point probe at the uniform-grid
+// guess.  grid_probe issues both probes, grid_finish reads the bounds off
+// them, so that the probes of several ranges can be in flight together.
+struct GridProbe {
+    Probe<2, double> a, b;
+    double va, vb;
+};
+__host__ __device__ __forceinline__ GridProbe grid_probe(const double *x, int n,
+                                                        double x0, double inv_dx,
+                                                        double va, double vb) {
+    return GridProbe{probe_at<2>(x, 0, n, grid_guess(x0, inv_dx, n, va)),
+                     probe_at<2>(x, 0, n, grid_guess(x0, inv_dx, n, vb)), va, vb};
+}
+__host__ __device__ inline int2 grid_finish(const double *x, int n,
+                                            const GridProbe &g) {
+    const double va = g.va, vb = g.vb;
+    auto ge = [&](double xi) { return !(xi < va); };
+    auto gt = [&](double xi) { return !(xi <= vb); };
+    const int na = probe_count(g.a, 0, n, ge), nb = probe_count(g.b, 0, n, gt);
+    return make_int2(probe_settle<2>(x, 0, n, g.a.j0, na, ge),
+                     probe_settle<2>(x, 0, n, g.b.j0, nb, gt));
+}
+__host__ __device__ inline int2 grid_range(const double *x, int n, double x0,
+                                           double inv_dx, double va,
+                                           double vb) {
+    return grid_finish(x, n, grid_probe(x, n, x0, inv_dx, va, vb));
 }
 
 // Full width of a peak centred at rho: w, or w / |cos(rho pi / 360)| with
@@ -284,11 +379,9 @@ __device__ inline int2 window_of(const ProbDev &P, double p, double mu,
                                  double w, double alpha) {
     if (P.cutoff == 0.0) return make_int2(0, P.N);
     const double2 ab = window_bounds<SEC>(P, p, mu, w, alpha);
-    const double a = ab.x, b = ab.y;
-    const int lo = lower_bound_x(P.x, P.N, P.x0, P.inv_dx, a);
-    int hi = upper_bound_x(P.x, P.N, P.x0, P.inv_dx, b);
-    if (hi < lo) hi = lo;
-    return make_int2(lo, hi);
+    int2 r = grid_range(P.x, P.N, P.x0, P.inv_dx, ab.x, ab.y);
+    if (r.y < r.x) r.y = r.x;
+    return r;
 }
 
 // ---- per-(sample, tile, phase) peak ranges ---------------------------------
@@ -297,39 +390,6 @@ __device__ inline int2 window_of(const ProbDev &P, double p, double mu,
 // the window bounds are monotone in the peak index and both the peaks whose
 // window reaches a tile and the peaks whose Gaussian matters there form
 // contiguous index ranges.
-
-// First j in [a, b) with v[j] > key (v non-decreasing).
-__device__ inline int first_greater(const int *v, int a, int b, int key) {
-    while (a < b) {
-        const int mid = (a + b) >> 1;
-        if (v[mid] > key) b = mid; else a = mid + 1;
-    }
-    return a;
-}
-// First j in [a, b) with v[j] >= key.
-__device__ inline int first_not_less(const int *v, int a, int b, int key) {
-    while (a < b) {
-        const int mid = (a + b) >> 1;
-        if (v[mid] >= key) b = mid; else a = mid + 1;
-    }
-    return a;
-}
-__device__ inline int first_not_less_d(const double *v, int a, int b,
-                                       double key) {
-    while (a < b) {
-        const int mid = (a + b) >> 1;
-        if (v[mid] >= key) b = mid; else a = mid + 1;
-    }
-    return a;
-}
-__device__ inline int first_greater_d(const double *v, int a, int b,
-                                      double key) {
-    while (a < b) {
-        const int mid = (a + b) >> 1;
-        if (v[mid] > key) b = mid; else a = mid + 1;
-    }
-    return a;
-}
 
 // First j in [a, b) with p[j] + mu > key (FP64 sum, as the peak centre
 // rho is formed everywhere else); monotone because p is sorted.
@@ -359,112 +419,130 @@ __device__ inline bool sec_monotone(double rf, double rl, double w, double R,
     return up > 0.0 && dn > 0.0;
 }
 
-// First j in [a, b) with pred(j) true (pred false then true over [a, b)).
-template <typename F>
-__host__ __device__ inline int first_true(int a, int b, F pred) {
-    while (a < b) {
-        const int mid = (a + b) >> 1;
-        if (pred(mid)) b = mid; else a = mid + 1;
-    }
-    return a;
-}
-
-// The same search started from a guess g: a few steps from the guess
-// checking the predicate, then bisection of what remains.
-template <typename F>
-__host__ __device__ inline int first_true_from(int a, int b, int g, F pred) {
-    g = g < a ? a : (g > b ? b : g);
-    int lo = a, hi = b;
-    for (int step = 0; step < 4; ++step) {
-        if (g > lo && pred(g - 1)) {            // answer at or left of g - 1
-            hi = g - 1;
-            --g;
-        } else if (g < hi && !pred(g)) {        // answer right of g
-            lo = g + 1;
-            ++g;
-        } else {
-            return g;
-        }
-    }
-    return first_true(lo, hi, pred);
-}
-
-// Guess for the first peak of phase k whose position is >= v.
-__device__ __forceinline__ int tab_guess(const ProbDev &P, int k, double v) {
+// Probe start for the first peak of phase k (peaks [a, b)) whose position
+// is >= v: one before the bucket's first peak, so that the probe also
+// covers an answer one to the left of it.
+__device__ __forceinline__ int tab_guess(const ProbDev &P, int k, double v,
+                                         int a, int b) {
     const double g = (v - P.tab_x0) * P.tab_inv;
-    const int b = !(g > 0.0) ? 0 : (g < (double)kTabBuckets ? (int)g : kTabBuckets);
-    return P.ptab[k * (kTabBuckets + 1) + b];
+    const int u = !(g > 0.0) ? 0 : (g < (double)kTabBuckets ? (int)g : kTabBuckets);
+    const int j = P.ptab[k * (kTabBuckets + 1) + u];
+    return (j < a ? a : (j > b ? b : j)) - 1;
+}
+
+// The peaks of phase k whose windows reach the points [xa, xb] of a tile
+// (sample row ph of phi): [ja, jb), from two searches over the phase's
+// sorted positions whose probes go out together, each predicate monotone
+// over the whole phase:
+//   ja: first peak whose window reaches xa (hi_j > i0 <=> x[i0] <= b_j),
+//   jb: first peak whose window starts past xb (lo_j >= i1 <=> a_j > x[i1-1]),
+// with the window bounds (a_j, b_j) formed as the window step forms them.
+// The searches start from position-index guesses (under the sec law the
+// width at the tile stands in for each peak's own: a guess only).  The
+// whole phase when there is no window or its sec-law bounds are not
+// monotone.  Also returns the phase's FP64 shift, width and alpha, and
+// whether the reach of the Gaussian fails to be monotone (sec law).
+struct PhaseWin {
+    int a, b, ja, jb;
+    double mu, w, alpha;
+    bool g_mono;
+};
+
+template <bool SEC>
+__device__ inline PhaseWin phase_window(const ProbDev &P, const double *ph,
+                                        int k, double xa, double xb) {
+#pragma clang fp contract(off)
+    PhaseWin r;
+    r.a = P.off[k];
+    r.b = P.off[k + 1];
+    const int a = r.a, b = r.b;
+    r.mu = ph[P.K + k];
+    r.w = ph[2 * P.K + k];
+    r.alpha = P.D == 5 ? ph[4 * P.K + k] : 1.0;
+    const double mu = r.mu, w = r.w, alpha = r.alpha;
+    bool win_mono = true;
+    r.g_mono = true;
+    if (SEC && a < b) {
+        const double rf = P.pos[a] + mu, rl = P.pos[b - 1] + mu;
+        win_mono = sec_monotone(rf, rl, w, P.cutoff, alpha);
+        r.g_mono = sec_monotone(rf, rl, w, kGaussReach, alpha);
+    }
+    r.ja = a;
+    r.jb = b;
+    if (!(P.cutoff > 0.0) || !win_mono) return r;
+    const double Wt = SEC ? peak_width<SEC>(xa, w) : w;
+    const double hw = P.cutoff * Wt, hwu = P.D == 5 ? hw * alpha : hw;
+    const Probe<4, double> pja = probe_at<4>(P.pos, a, b, tab_guess(P, k, xa - mu - hwu, a, b));
+    const Probe<4, double> pjb = probe_at<4>(P.pos, a, b, tab_guess(P, k, xb - mu + hw, a, b));
+    auto reach_a = [&](double p) {          // window reaches xa
+        return xa <= window_bounds<SEC>(P, p, mu, w, alpha).y;
+    };
+    auto past_b = [&](double p) {           // window starts past xb
+        return window_bounds<SEC>(P, p, mu, w, alpha).x > xb;
+    };
+    const int nja = probe_count(pja, a, b, reach_a);
+    const int njb = probe_count(pjb, a, b, past_b);
+    r.ja = probe_settle<4>(P.pos, a, b, pja.j0, nja, reach_a);
+    r.jb = probe_settle<4>(P.pos, a, b, pjb.j0, njb, past_b);
+    if (r.jb < r.ja) r.jb = r.ja;
+    return r;
+}
+
+// The peaks of [ja, jb) whose Gaussian reaches the tile [xa, xb]: [ga, gb),
+// searched like [ja, jb) over the positions and clamped into it.  Reach of
+// a peak: [rho - R W, rho + R alpha W] with R = kGaussReach; ga is the first
+// peak whose reach ends at or past xa, gb the first whose reach starts past
+// xb.  Under the sec law with a non-monotone reach, all of [ja, jb).
+template <bool SEC>
+__device__ inline int2 gauss_range(const ProbDev &P, const PhaseWin &pw, int k,
+                                   double xa, double xb) {
+#pragma clang fp contract(off)
+    const int a = pw.a, b = pw.b, ja = pw.ja, jb = pw.jb;
+    if (SEC && !pw.g_mono) return make_int2(ja, jb);
+    const double mu = pw.mu, w = pw.w, alpha = pw.alpha;
+    const double Wt = SEC ? peak_width<SEC>(xa, w) : w;
+    const double rg = kGaussReach * Wt, rgu = rg * alpha;
+    const Probe<4, double> pga = probe_at<4>(P.pos, a, b, tab_guess(P, k, xa - mu - rgu, a, b));
+    const Probe<4, double> pgb = probe_at<4>(P.pos, a, b, tab_guess(P, k, xb - mu + rg, a, b));
+    auto g_a = [&](double p) {
+        if (!SEC) return p >= xa - mu - kGaussReach * w * alpha;
+        const double rho = p + mu;
+        return rho + kGaussReach * peak_width<SEC>(rho, w) * alpha >= xa;
+    };
+    auto g_b = [&](double p) {
+        if (!SEC) return p > xb - mu + kGaussReach * w;
+        const double rho = p + mu;
+        return rho - kGaussReach * peak_width<SEC>(rho, w) > xb;
+    };
+    const int nga = probe_count(pga, a, b, g_a);
+    const int ngb = probe_count(pgb, a, b, g_b);
+    int ga = probe_settle<4>(P.pos, a, b, pga.j0, nga, g_a);
+    int gb = probe_settle<4>(P.pos, a, b, pgb.j0, ngb, g_b);
+    ga = ga < ja ? ja : (ga > jb ? jb : ga);
+    gb = gb < ga ? ga : (gb > jb ? jb : gb);
+    return make_int2(ga, gb);
 }
 
 // Range entry of (sample s, tile t, phase k); phi: [S][D][K].  For
 // asymmetric peaks *side receives (jr, jl) with ga <= jr <= jl <= gb.
 // Ranges may be wider than needed (the windowed kernels mask each peak by
 // its exact window); with the sec law they cover the whole phase when its
-// bounds are not monotone.
+// bounds are not monotone.  [ja, jb) as phase_window, [ga, gb) as
+// gauss_range.
 template <bool SEC>
-__device__ inline int4 tile_range(const ProbDev &P, const StepDev &st,
-                                  const double *phi, int s, int t, int k,
-                                  int2 *side) {
+__device__ inline int4 tile_range(const ProbDev &P, const double *phi, int s,
+                                  int t, int k, int2 *side) {
 #pragma clang fp contract(off)
-    const int a = P.off[k], b = P.off[k + 1];
     const int i0 = t * kTile, i1 = min(i0 + kTile, P.N);
-    const double *ph = phi + (size_t)s * P.D * P.K;
-    const double mu = ph[P.K + k], w = ph[2 * P.K + k];
-    const double alpha = P.D == 5 ? ph[4 * P.K + k] : 1.0;
-    bool win_mono = true, g_mono = true;
-    if (SEC && a < b) {
-        const double rf = P.pos[a] + mu, rl = P.pos[b - 1] + mu;
-        win_mono = sec_monotone(rf, rl, w, P.cutoff, alpha);
-        g_mono = sec_monotone(rf, rl, w, kGaussReach, alpha);
-    }
     const double xa = P.x[i0], xb = P.x[i1 - 1];
-    int ja = a, jb = b;
-    if (P.cutoff > 0.0 && win_mono) {
-        if (!SEC) {
-            // hi_j > i0 <=> x[i0] <= b_j and lo_j >= i1 <=> a_j > x[i1 - 1],
-            // with the window bounds (a_j, b_j) formed as the window step
-            // forms them; searched over the positions from a table guess
-            const double hw = P.cutoff * w;
-            const double hwu = P.D == 5 ? hw * alpha : hw;
-            ja = first_true_from(a, b, tab_guess(P, k, xa - mu - hwu), [&](int j) {
-                return xa <= window_bounds<false>(P, P.pos[j], mu, w, alpha).y;
-            });
-            jb = first_true_from(ja, b, tab_guess(P, k, xb - mu + hw), [&](int j) {
-                return window_bounds<false>(P, P.pos[j], mu, w, alpha).x > xb;
-            });
-        } else {
-            const int *lo = st.lo + (size_t)s * P.T;
-            const int *hi = st.hi + (size_t)s * P.T;
-            ja = first_greater(hi, a, b, i0);
-            jb = first_not_less(lo, ja, b, i1);
-        }
-    }
-    int ga = ja, gb = jb;
-    if (!SEC) {
-        const double reach = kGaussReach * w;       // below rho
-        const double reach_hi = reach * alpha;      // above rho
-        // Gaussian relevant: p + mu + reach_hi >= x[i0], p + mu - reach <= x[i1-1]
-        const double ka = xa - mu - reach_hi, kb = xb - mu + reach;
-        ga = first_true_from(ja, jb, tab_guess(P, k, ka),
-                             [&](int j) { return P.pos[j] >= ka; });
-        gb = first_true_from(ga, jb, tab_guess(P, k, kb),
-                             [&](int j) { return P.pos[j] > kb; });
-    } else if (g_mono) {
-        ga = first_true(ja, jb, [&](int j) {
-            const double rho = P.pos[j] + mu;
-            return rho + kGaussReach * peak_width<SEC>(rho, w) * alpha >= xa;
-        });
-        gb = first_true(ga, jb, [&](int j) {
-            const double rho = P.pos[j] + mu;
-            return rho - kGaussReach * peak_width<SEC>(rho, w) > xb;
-        });
-    }
+    const PhaseWin pw = phase_window<SEC>(P, phi + (size_t)s * P.D * P.K, k, xa, xb);
+    const int2 g = gauss_range<SEC>(P, pw, k, xa, xb);
     if (side) {
-        const int jr = first_centre_above(P.pos, ga, gb, mu, P.x[i0]);
-        const int jl = first_centre_above(P.pos, jr, gb, mu, P.x[i1 - 1]);
+        const int jr = first_centre_above(P.pos, g.x, g.y, pw.mu, xa);
+        const int jl = first_centre_above(P.pos, jr, g.y, pw.mu, xb);
         *side = make_int2(jr, jl);
     }
-    return make_int4(ja, ga, gb, jb);
+    return make_int4(pw.ja, g.x, g.y, pw.jb);
 }
 
 // ---- wave reductions ------------------------------------------------------
@@ -918,10 +996,13 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
 // relative to the tile, 2 c / (A w) below and above the centre (c = 1 without
 // the sec law; A = 1 below, alpha above), the Lorentzian and Gaussian
 // amplitudes I h r cL n / w and I h (1 - r) cG n / w (times c with the sec
-// law; the Gaussian one 0 where that term is negligible) and the window.
-// One thread per phase finds its phase's peak ranges over the tile and
-// writes its records, then the waves share the flat list.  Phases whose records do not fit the staging space (they come
-// last in the chunk) are evaluated from global memory, phase by phase.
+// law) and the window.  One thread per phase finds its phase's peak ranges
+// over the tile and writes its records: those whose Gaussian reaches the
+// tile from the front of the list, the others (Lorentzian only) from the
+// back, so that each part is evaluated by a loop without a per-record
+// branch.  The waves then share both parts.  Phases whose records do not
+// fit the staging space (they come last in the chunk) are evaluated from
+// global memory, phase by phase.
 constexpr int kWinChunk = kBlock;   // phases staged at a time (one per thread)
 constexpr int kWinPeaks = 1024;     // staged peak records per chunk
 
@@ -943,7 +1024,7 @@ template <bool ASYM>
 struct WinSmem {
     float4 rec[kWinPeaks];          // (centre, 2c/(Aw) below, amp L, amp G)
     WinRec2<ASYM> rec2[kWinPeaks];  // (lo, hi[, 2c/(alpha w)])
-    int wmax[kWaves], wcnt[kWaves];
+    int wmax[kWaves], wmaxn[kWaves], wcnt[kWaves], wcntg[kWaves];
     float sig[kWaves][kTile];
     float rres[kTile];
     double red[kWaves];
@@ -987,6 +1068,43 @@ __device__ void win_phase_global(const SegPeaks &sp, int4 r, int2 r2,
         sig[p] = fmaf(aL, accL[p], fmaf(aG, accG[p], sig[p]));
 }
 
+// One staged record's terms at the lane's points (a: centre, scale below,
+// Lorentzian and Gaussian amplitudes; b: window and the scale above).
+template <bool ASYM, bool GAUSS>
+__device__ __forceinline__ void win_record(const float4 a, const WinRec2<ASYM> b,
+                                           const float (&u)[kPPL],
+                                           const int (&idx)[kPPL],
+                                           float (&sig)[kPPL]) {
+    const float ah = b.ahi(a.y);
+    const unsigned span = (unsigned)(b.hi - b.lo);
+#pragma unroll
+    for (int p = 0; p < kPPL; ++p) {
+        // only the lanes whose point lies in the window take part: a half
+        // tile the window misses is skipped by the whole wave
+        if ((unsigned)(idx[p] - b.lo) < span) {
+            const float d = u[p] - a.x;
+            const float q2 = d * (ASYM ? (d >= 0.f ? ah : a.y) : a.y);
+            const float tt = fmaf(q2, q2, 1.0f);
+            sig[p] = fmaf(a.z, rcp_f32(tt), sig[p]);
+            if (GAUSS) sig[p] = fmaf(a.w, exp2_f32(1.0f - tt), sig[p]);
+        }
+    }
+}
+
+// Block order of the windowed forward.  The hardware deals consecutive
+// blocks to the 8 XCDs in turn; block b takes (tile, sample) pairs from the
+// (b mod 8)-th contiguous run of the tile-major, sample-fastest order, so
+// each XCD's L2 holds the peak data near its own run of tiles.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int2 xcd_tile_sample(int ntiles, int S) {
+    const int nb = ntiles * S;
+    const int b = blockIdx.x + blockIdx.y * gridDim.x;
+    const int per = nb / kXcds, rem = nb % kXcds;
+    const int x = b % kXcds, i = b / kXcds;
+    const int q = x * per + min(x, rem) + i;
+    return make_int2(q / S, q % S);
+}
+
 template <bool ASYM, bool SEC>
 __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
                          float *f_out, WinSmem<ASYM> &sm) {
@@ -1002,6 +1120,9 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
     const int *whi = st.hi + (size_t)s * P.T;
     const float *psec = SEC ? reinterpret_cast<const float *>(st.psec + (size_t)s * P.T)
                             : nullptr;
+    const double *ph = st.phi + (size_t)s * P.D * K;
+    const double xref = P.x[min(i0 + kTile / 2, P.N - 1)];   // the tile's reference
+    const double xa = P.x[i0], xb = P.x[min(i0 + kTile, P.N) - 1];
     SegPeaks sp;
     sp.pt = as_const(ptt);
     sp.inten = as_const(P.inten);
@@ -1021,99 +1142,106 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
 
     for (int c0 = 0; c0 < K; c0 += kWinChunk) {
         const int nk = min(kWinChunk, K - c0);
-        // this thread's phase: its peak ranges over the tile (found here:
-        // the windowed forward is their only user), constants and count
-        int4 r = make_int4(0, 0, 0, 0);
-        int2 r2 = make_int2(0, 0);
+        // this thread's phase: the peaks whose windows reach the tile and,
+        // among them, those whose Gaussian does (found here: the windowed
+        // forward is their only user), constants and counts
+        PhaseWin pw{0, 0, 0, 0, 0.0, 0.0, 1.0, true};
+        int2 gr = make_int2(0, 0);
         float4 cst = make_float4(0.f, 0.f, 0.f, 0.f);
         float iw2r = 0.f;
         if (tid < nk) {
             cst = pkv[c0 + tid];
             if (ASYM) iw2r = pkrv[c0 + tid];
-            r = tile_range<SEC>(P, st, st.phi, s, t, c0 + tid, ASYM ? &r2 : nullptr);
+            pw = phase_window<SEC>(P, ph, c0 + tid, xa, xb);
+            gr = gauss_range<SEC>(P, pw, c0 + tid, xa, xb);
         }
-        const int cnt = r.w - r.x;
-        // inclusive prefix of the counts over the block
-        int incl = cnt;
+        const int cnt = pw.jb - pw.ja, cg = gr.y - gr.x;
+        // inclusive prefixes over the block of the record counts and of the
+        // Gaussian record counts
+        int incl = cnt, inclg = cg;
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
             const int v = __shfl_up(incl, o, kWave);
-            if (lane >= o) incl += v;
+            const int vg = __shfl_up(inclg, o, kWave);
+            if (lane >= o) { incl += v; inclg += vg; }
         }
-        if (lane == kWave - 1) sm.wcnt[wv] = incl;
+        if (lane == kWave - 1) { sm.wcnt[wv] = incl; sm.wcntg[wv] = inclg; }
         __syncthreads();
-        int before = 0;
-        for (int w = 0; w < wv; ++w) before += sm.wcnt[w];
-        incl += before;
-        const int excl = incl - cnt;
+        for (int w = 0; w < wv; ++w) { incl += sm.wcnt[w]; inclg += sm.wcntg[w]; }
+        const int excl = incl - cnt, exclg = inclg - cg, excln = excl - exclg;
         // records of the phases that fit (a prefix of the chunk: incl grows
-        // with the phase index)
+        // with the phase index).  Records with a Gaussian fill the list from
+        // the front, the others from the back, each in phase and peak order.
         const bool fits = tid < nk && incl <= kWinPeaks;
         if (fits) {
             const float iw2 = cst.x, aG = cst.y, aL = cst.z, mu = cst.w;
+            // The tile-relative centre comes from the FP64 position (as the
+            // per-tile table is formed), the window from the window step's
+            // own bounds and grid search, and the side of an asymmetric peak
+            // from the predicates of the tile plan's side searches.
             for (int q = 0; q < cnt; ++q) {
-                const int j = r.x + q;
-                float I = P.inten[j], c = 1.f;
-                if (SEC) {
-                    c = psec[4 * j];
-                    I = psec[4 * j + 1];
-                }
+                const int j = pw.ja + q;
+                const double pj = P.pos[j];
+                const float I = SEC ? psec[4 * j + 1] : P.inten[j];
+                const float c = SEC ? psec[4 * j] : 1.f;
+                const double2 ab = window_bounds<SEC>(P, pj, pw.mu, pw.w, pw.alpha);
+                const GridProbe gp = grid_probe(P.x, P.N, P.x0, P.inv_dx, ab.x, ab.y);
                 float alo = iw2 * c, ahi = alo;
                 if (ASYM) {
+                    // centre at or below the tile's first point: the tile
+                    // lies above it; at or below its last: it straddles it
                     const float ar = iw2r * c;
-                    if (j < r2.x) alo = ahi = ar;     // tile above the centre
-                    else if (j < r2.y) ahi = ar;      // tile straddles it
+                    const double rho = pj + pw.mu;
+                    if (!(rho > xa)) alo = ahi = ar;
+                    else if (!(rho > xb)) ahi = ar;
                 }
-                const bool gauss = j >= r.y && j < r.z;
-                sm.rec[excl + q] = make_float4(ptt[j] + mu, alo, I * aL,
-                                               gauss ? I * aG : 0.f);
+                const bool gauss = j >= gr.x && j < gr.y;
+                const int slot = gauss ? exclg + (j - gr.x)
+                                       : kWinPeaks - 1 - excln -
+                                             (j < gr.x ? j - pw.ja : q - cg);
+                sm.rec[slot] = make_float4((float)(pj - xref) + mu, alo, I * aL,
+                                           gauss ? I * aG : 0.f);
+                const int2 wnd = grid_finish(P.x, P.N, gp);
                 WinRec2<ASYM> w2;
-                w2.lo = wlo[j];
-                w2.hi = whi[j];
+                w2.lo = wnd.x;
+                w2.hi = wnd.y < wnd.x ? wnd.x : wnd.y;
                 if constexpr (ASYM) { w2.ah = ahi; w2.pad = 0.f; }
-                sm.rec2[excl + q] = w2;
+                sm.rec2[slot] = w2;
             }
         }
-        // staged record count and number of fitting phases
-        const int nrec = wave_max_i32(fits ? incl : 0);
+        // staged record counts and number of fitting phases
+        const int ng = wave_max_i32(fits ? inclg : 0);
+        const int nn = wave_max_i32(fits ? incl - inclg : 0);
         const int nfit = __builtin_popcountll(__ballot(fits));
         __syncthreads();                       // prefix words read, records written
-        if (lane == 0) { sm.wmax[wv] = nrec; }
-        if (lane == 1) { sm.wcnt[wv] = nfit; }
+        if (lane == 0) { sm.wmax[wv] = ng; }
+        if (lane == 1) { sm.wmaxn[wv] = nn; }
+        if (lane == 2) { sm.wcnt[wv] = nfit; }
         __syncthreads();
-        int n_flat = 0, n_fit = 0;
+        int n_g = 0, n_n = 0, n_fit = 0;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
-            n_flat = max(n_flat, sm.wmax[w]);
+            n_g = max(n_g, sm.wmax[w]);
+            n_n = max(n_n, sm.wmaxn[w]);
             n_fit += sm.wcnt[w];
         }
-        n_flat = __builtin_amdgcn_readfirstlane(n_flat);
+        n_g = __builtin_amdgcn_readfirstlane(n_g);
+        n_n = __builtin_amdgcn_readfirstlane(n_n);
         n_fit = __builtin_amdgcn_readfirstlane(n_fit);
 
-        // the waves share the flat list
+        // the waves share the two lists
 #pragma unroll 2
-        for (int f = wv; f < n_flat; f += kWaves) {
-            const float4 a = sm.rec[f];
-            const WinRec2<ASYM> b = sm.rec2[f];
-            const float ah = b.ahi(a.y);
-            const bool g = __builtin_amdgcn_readfirstlane(__float_as_int(a.w)) != 0;
-            PeakMask<true> mk;
-            mk.lo = b.lo;
-            mk.hi = b.hi;
-#pragma unroll
-            for (int p = 0; p < kPPL; ++p) {
-                const float d = u[p] - a.x;
-                const float q2 = d * (ASYM ? (d >= 0.f ? ah : a.y) : a.y);
-                const float tt = mk.apply(idx[p], fmaf(q2, q2, 1.0f));
-                sig[p] = fmaf(a.z, rcp_f32(tt), sig[p]);
-                if (g) sig[p] = fmaf(a.w, exp2_f32(1.0f - tt), sig[p]);
-            }
-        }
+        for (int f = wv; f < n_g; f += kWaves)
+            win_record<ASYM, true>(sm.rec[f], sm.rec2[f], u, idx, sig);
+#pragma unroll 2
+        for (int f = wv; f < n_n; f += kWaves)
+            win_record<ASYM, false>(sm.rec[kWinPeaks - 1 - f],
+                                    sm.rec2[kWinPeaks - 1 - f], u, idx, sig);
         // phases that did not fit (every lane finds the same ranges)
         for (int kl = n_fit + wv; kl < nk; kl += kWaves) {
             const int k = c0 + kl;
             int2 rk2 = make_int2(0, 0);
-            const int4 rk = tile_range<SEC>(P, st, st.phi, s, t, k, ASYM ? &rk2 : nullptr);
+            const int4 rk = tile_range<SEC>(P, st.phi, s, t, k, ASYM ? &rk2 : nullptr);
             win_phase_global<ASYM, SEC>(sp, rk, rk2, pkv[k], ASYM ? pkrv[k] : 0.f,
                                         u, idx, sig);
         }

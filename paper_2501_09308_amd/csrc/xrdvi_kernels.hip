@@ -97,13 +97,16 @@ __global__ __launch_bounds__(kWideWaves * kWave) void k_fused_wide(ProbDev P, St
     fused_tile<false, GRAD, ASYM, SEC, kWideWaves>(P, st, blockIdx.x, blockIdx.y, f_out, sm);
 }
 
-// a3 + a4 (windowed): forward tile over its flat list of staged peak
-// records; grid (ntiles, S), kBlock threads.
+// a3 + a4 (windowed): forward tile over its staged peak records; grid
+// (ntiles, S), kBlock threads, blocks ordered by XCD.  The register budget
+// is held to the occupancy the staging space allows (six blocks per CU, four
+// with asymmetric records; the sec-law variants are left unbounded).
 template <bool ASYM, bool SEC>
-__global__ __launch_bounds__(kBlock) void k_win(ProbDev P, StepDev st,
+__global__ __launch_bounds__(kBlock, SEC ? 1 : (ASYM ? 4 : 6)) void k_win(ProbDev P, StepDev st,
                                                 float *f_out) {
     __shared__ WinSmem<ASYM> sm;
-    win_tile<ASYM, SEC>(P, st, blockIdx.x, blockIdx.y, f_out, sm);
+    const int2 ts = xcd_tile_sample(P.ntiles, st.S);
+    win_tile<ASYM, SEC>(P, st, ts.x, ts.y, f_out, sm);
 }
 
 // a6 (windowed): peak-major adjoint, one block per (sample, phase);

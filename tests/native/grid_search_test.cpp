@@ -1,6 +1,7 @@
-// Host check of the guessed-then-walked grid search against std::lower_bound
-// and std::upper_bound on uniform, jittered and strongly non-uniform grids,
-// and of the guessed predicate search against a plain scan.
+// Host check of the grid searches (guessed then walked, and the batched
+// two-point probes) against std::lower_bound and std::upper_bound on
+// uniform, jittered and strongly non-uniform grids, and of the batched
+// predicate search against a plain scan.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -38,20 +39,21 @@ int main() {
             else val = std::nan("");
             const int lo = xrdvi::grid_bound<false>(x.data(), n, x0, inv, val);
             const int hi = xrdvi::grid_bound<true>(x.data(), n, x0, inv, val);
+            const int2 pr = xrdvi::grid_range(x.data(), n, x0, inv, val, val);
             int rlo = (int)(std::lower_bound(x.begin(), x.end(), val) - x.begin());
             int rhi = (int)(std::upper_bound(x.begin(), x.end(), val) - x.begin());
             // NaN compares false with everything: both bounds are 0 (the
             // window plan then gives an empty window)
             if (std::isnan(val)) rlo = rhi = 0;
-            checks += 2;
-            if (lo != rlo || hi != rhi) {
-                if (bad < 5) std::printf("n=%d kind=%d v=%.17g: %d %d vs %d %d\n", n, kind, val, lo, hi, rlo, rhi);
+            checks += 4;
+            if (lo != rlo || hi != rhi || pr.x != rlo || pr.y != rhi) {
+                if (bad < 5) std::printf("n=%d kind=%d v=%.17g: %d %d / %d %d vs %d %d\n", n, kind, val, lo, hi, pr.x, pr.y, rlo, rhi);
                 ++bad;
             }
         }
     }
-    // searches of a monotone predicate started from any guess (the tile
-    // plan's searches over peak positions) against a plain scan
+    // batched searches of a monotone predicate from any probe position (the
+    // tile plan's searches over peak positions) against a plain scan
     for (int g = 0; g < 2000; ++g) {
         const int n = (int)(U(rng) * 200);
         std::vector<double> p(n);
@@ -61,15 +63,16 @@ int main() {
         const int b = a + (int)(U(rng) * (n - a + 1));
         for (int q = 0; q < 20; ++q) {
             const double key = -1.0 + (v + 2.0) * U(rng);
-            const int guess = -5 + (int)(U(rng) * (n + 10));
-            auto pred = [&](int j) { return p[j] >= key; };
+            const int j0 = -5 + (int)(U(rng) * (n + 10));
+            auto pred = [&](double pv) { return pv >= key; };
             int ref = a;
-            while (ref < b && !pred(ref)) ++ref;
-            const int got = xrdvi::first_true_from(a, b, guess, pred);
-            const int got0 = xrdvi::first_true(a, b, pred);
+            while (ref < b && !pred(p[ref])) ++ref;
+            const double *pp = n ? p.data() : &key;
+            const int got4 = xrdvi::probe_result(pp, a, b, xrdvi::probe_at<4>(pp, a, b, j0), pred);
+            const int got2 = xrdvi::probe_result(pp, a, b, xrdvi::probe_at<2>(pp, a, b, j0), pred);
             checks += 2;
-            if (got != ref || got0 != ref) {
-                if (bad < 5) std::printf("n=%d [%d,%d) guess=%d: %d %d vs %d\n", n, a, b, guess, got, got0, ref);
+            if (got4 != ref || got2 != ref) {
+                if (bad < 5) std::printf("n=%d [%d,%d) j0=%d: %d %d vs %d\n", n, a, b, j0, got4, got2, ref);
                 ++bad;
             }
         }
