@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void kb_plan(const SlotDev *tab,
 }
 
 template <bool WIN, bool ASYM, bool SEC>
-__global__ __launch_bounds__(kBlock, WIN && !SEC ? (ASYM ? 4 : 6) : 1) void kb_fused(const SlotDev *tab,
+__global__ __launch_bounds__(kBlock) void kb_fused(const SlotDev *tab,
                                                    const SchedDev *sch) {
     using Smem = typename std::conditional<WIN, WinSmem<ASYM>, FusedSmem>::type;
     __shared__ PrefixSmem ps;

@@ -1091,10 +1091,11 @@ __device__ __forceinline__ void win_record(const float4 a, const WinRec2<ASYM> b
     }
 }
 
-// Block order of the windowed forward.  The hardware deals consecutive
-// blocks to the 8 XCDs in turn; block b takes (tile, sample) pairs from the
-// (b mod 8)-th contiguous run of the tile-major, sample-fastest order, so
-// each XCD's L2 holds the peak data near its own run of tiles.
+// Block order of the kernels over (tile, sample) grids.  The hardware deals
+// consecutive blocks to the 8 XCDs in turn; block b takes (tile, sample)
+// pairs from the (b mod 8)-th contiguous run of the tile-major,
+// sample-fastest order, so each XCD's L2 holds the peak data near its own
+// run of tiles.
 constexpr int kXcds = 8;
 __device__ __forceinline__ int2 xcd_tile_sample(int ntiles, int S) {
     const int nb = ntiles * S;

@@ -78,12 +78,15 @@ __global__ void k_plan(ProbDev P, StepDev st, const double *__restrict__ phi) {
         plan_elem<SEC>(P, st, phi, g);
 }
 
-// a3 + a4 (+ a6): grid (ntiles, S), kBlock threads.
+// a3 + a4 (+ a6): grid (ntiles, S), kBlock threads, blocks ordered by XCD
+// (the samples of a tile share its positions and counts in one L2, and
+// their adjoint partials, adjacent in memory, merge there before write-back).
 template <bool WIN, bool GRAD, bool ASYM, bool SEC>
 __global__ __launch_bounds__(kBlock) void k_fused(ProbDev P, StepDev st,
                                                   float *f_out) {
     __shared__ FusedSmem sm;
-    fused_tile<WIN, GRAD, ASYM, SEC>(P, st, blockIdx.x, blockIdx.y, f_out, sm);
+    const int2 ts = xcd_tile_sample(P.ntiles, st.S);
+    fused_tile<WIN, GRAD, ASYM, SEC>(P, st, ts.x, ts.y, f_out, sm);
 }
 
 // Dense a3 + a4 + a6 with kWideWaves waves per tile, for grids of too few
