@@ -430,18 +430,19 @@ __device__ __forceinline__ int tab_guess(const ProbDev &P, int k, double v,
     return (j < a ? a : (j > b ? b : j)) - 1;
 }
 
-// The peaks of phase k whose windows reach the points [xa, xb] of a tile
-// (sample row ph of phi): [ja, jb), from two searches over the phase's
-// sorted positions whose probes go out together, each predicate monotone
-// over the whole phase:
-//   ja: first peak whose window reaches xa (hi_j > i0 <=> x[i0] <= b_j),
-//   jb: first peak whose window starts past xb (lo_j >= i1 <=> a_j > x[i1-1]),
+// The peaks of phase k whose windows reach the points [xa, xb] = x[i0 ..
+// i1-1] of a tile (sample row ph of phi, window arrays wlo / whi of that
+// sample): [ja, jb), from two searches whose probes go out together, each
+// predicate monotone over the whole phase:
+//   ja: first peak whose window reaches the tile, hi_j > i0 <=> xa <= b_j,
+//   jb: first peak whose window starts past it, lo_j >= i1 <=> a_j > xb,
 // with the window bounds (a_j, b_j) formed as the window step forms them.
-// The searches start from position-index guesses (under the sec law the
-// width at the tile stands in for each peak's own: a guess only).  The
-// whole phase when there is no window or its sec-law bounds are not
-// monotone.  Also returns the phase's FP64 shift, width and alpha, and
-// whether the reach of the Gaussian fails to be monotone (sec law).
+// The searches start from position-index guesses.  With a constant width
+// they test the positions; under the sec law (whose bounds need a cosine
+// per peak) they test the window step's index arrays.  The whole phase
+// when there is no window or its sec-law bounds are not monotone.  Also
+// returns the phase's FP64 shift, width and alpha, and whether the reach
+// of the Gaussian is monotone (sec law).
 struct PhaseWin {
     int a, b, ja, jb;
     double mu, w, alpha;
@@ -450,7 +451,8 @@ struct PhaseWin {
 
 template <bool SEC>
 __device__ inline PhaseWin phase_window(const ProbDev &P, const double *ph,
-                                        int k, double xa, double xb) {
+                                        int k, int i0, int i1, const int *wlo,
+                                        const int *whi) {
 #pragma clang fp contract(off)
     PhaseWin r;
     r.a = P.off[k];
@@ -460,6 +462,7 @@ __device__ inline PhaseWin phase_window(const ProbDev &P, const double *ph,
     r.w = ph[2 * P.K + k];
     r.alpha = P.D == 5 ? ph[4 * P.K + k] : 1.0;
     const double mu = r.mu, w = r.w, alpha = r.alpha;
+    const double xa = P.x[i0], xb = P.x[i1 - 1];
     bool win_mono = true;
     r.g_mono = true;
     if (SEC && a < b) {
@@ -470,50 +473,74 @@ __device__ inline PhaseWin phase_window(const ProbDev &P, const double *ph,
     r.ja = a;
     r.jb = b;
     if (!(P.cutoff > 0.0) || !win_mono) return r;
-    const double Wt = SEC ? peak_width<SEC>(xa, w) : w;
+    const double Wt = SEC ? peak_width<SEC>(xa, w) : w;   // a guess only
     const double hw = P.cutoff * Wt, hwu = P.D == 5 ? hw * alpha : hw;
-    const Probe<4, double> pja = probe_at<4>(P.pos, a, b, tab_guess(P, k, xa - mu - hwu, a, b));
-    const Probe<4, double> pjb = probe_at<4>(P.pos, a, b, tab_guess(P, k, xb - mu + hw, a, b));
-    auto reach_a = [&](double p) {          // window reaches xa
-        return xa <= window_bounds<SEC>(P, p, mu, w, alpha).y;
-    };
-    auto past_b = [&](double p) {           // window starts past xb
-        return window_bounds<SEC>(P, p, mu, w, alpha).x > xb;
-    };
-    const int nja = probe_count(pja, a, b, reach_a);
-    const int njb = probe_count(pjb, a, b, past_b);
-    r.ja = probe_settle<4>(P.pos, a, b, pja.j0, nja, reach_a);
-    r.jb = probe_settle<4>(P.pos, a, b, pjb.j0, njb, past_b);
+    const int g_a = tab_guess(P, k, xa - mu - hwu, a, b);
+    const int g_b = tab_guess(P, k, xb - mu + hw, a, b);
+    if (SEC) {
+        const Probe<4, int> pja = probe_at<4>(whi, a, b, g_a);
+        const Probe<4, int> pjb = probe_at<4>(wlo, a, b, g_b);
+        auto reach_a = [&](int hi) { return hi > i0; };
+        auto past_b = [&](int lo) { return lo >= i1; };
+        const int nja = probe_count(pja, a, b, reach_a);
+        const int njb = probe_count(pjb, a, b, past_b);
+        r.ja = probe_settle<4>(whi, a, b, pja.j0, nja, reach_a);
+        r.jb = probe_settle<4>(wlo, a, b, pjb.j0, njb, past_b);
+    } else {
+        const Probe<4, double> pja = probe_at<4>(P.pos, a, b, g_a);
+        const Probe<4, double> pjb = probe_at<4>(P.pos, a, b, g_b);
+        auto reach_a = [&](double p) {
+            return xa <= window_bounds<SEC>(P, p, mu, w, alpha).y;
+        };
+        auto past_b = [&](double p) {
+            return window_bounds<SEC>(P, p, mu, w, alpha).x > xb;
+        };
+        const int nja = probe_count(pja, a, b, reach_a);
+        const int njb = probe_count(pjb, a, b, past_b);
+        r.ja = probe_settle<4>(P.pos, a, b, pja.j0, nja, reach_a);
+        r.jb = probe_settle<4>(P.pos, a, b, pjb.j0, njb, past_b);
+    }
     if (r.jb < r.ja) r.jb = r.ja;
     return r;
 }
 
 // The peaks of [ja, jb) whose Gaussian reaches the tile [xa, xb]: [ga, gb),
-// searched like [ja, jb) over the positions and clamped into it.  Reach of
-// a peak: [rho - R W, rho + R alpha W] with R = kGaussReach; ga is the first
-// peak whose reach ends at or past xa, gb the first whose reach starts past
-// xb.  Under the sec law with a non-monotone reach, all of [ja, jb).
+// clamped into [ja, jb).  Reach of a peak: [rho - R W, rho + R alpha W] with
+// R = kGaussReach; ga is the first peak whose reach ends at or past xa, gb
+// the first whose reach starts past xb.  With a constant width, searched
+// like [ja, jb) over the positions; under the sec law by bisection of the
+// few peaks of [ja, jb) (a cosine per test), and all of them when the reach
+// is not monotone.
 template <bool SEC>
 __device__ inline int2 gauss_range(const ProbDev &P, const PhaseWin &pw, int k,
                                    double xa, double xb) {
 #pragma clang fp contract(off)
     const int a = pw.a, b = pw.b, ja = pw.ja, jb = pw.jb;
-    if (SEC && !pw.g_mono) return make_int2(ja, jb);
     const double mu = pw.mu, w = pw.w, alpha = pw.alpha;
-    const double Wt = SEC ? peak_width<SEC>(xa, w) : w;
-    const double rg = kGaussReach * Wt, rgu = rg * alpha;
+    if (SEC) {
+        if (!pw.g_mono) return make_int2(ja, jb);
+        auto bisect = [&](int lo, int hi, auto pred) {
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (pred(P.pos[mid])) hi = mid; else lo = mid + 1;
+            }
+            return lo;
+        };
+        const int ga = bisect(ja, jb, [&](double p) {
+            const double rho = p + mu;
+            return rho + kGaussReach * peak_width<SEC>(rho, w) * alpha >= xa;
+        });
+        const int gb = bisect(ga, jb, [&](double p) {
+            const double rho = p + mu;
+            return rho - kGaussReach * peak_width<SEC>(rho, w) > xb;
+        });
+        return make_int2(ga, gb);
+    }
+    const double rg = kGaussReach * w, rgu = rg * alpha;
     const Probe<4, double> pga = probe_at<4>(P.pos, a, b, tab_guess(P, k, xa - mu - rgu, a, b));
     const Probe<4, double> pgb = probe_at<4>(P.pos, a, b, tab_guess(P, k, xb - mu + rg, a, b));
-    auto g_a = [&](double p) {
-        if (!SEC) return p >= xa - mu - kGaussReach * w * alpha;
-        const double rho = p + mu;
-        return rho + kGaussReach * peak_width<SEC>(rho, w) * alpha >= xa;
-    };
-    auto g_b = [&](double p) {
-        if (!SEC) return p > xb - mu + kGaussReach * w;
-        const double rho = p + mu;
-        return rho - kGaussReach * peak_width<SEC>(rho, w) > xb;
-    };
+    auto g_a = [&](double p) { return p >= xa - mu - kGaussReach * w * alpha; };
+    auto g_b = [&](double p) { return p > xb - mu + kGaussReach * w; };
     const int nga = probe_count(pga, a, b, g_a);
     const int ngb = probe_count(pgb, a, b, g_b);
     int ga = probe_settle<4>(P.pos, a, b, pga.j0, nga, g_a);
@@ -530,12 +557,15 @@ __device__ inline int2 gauss_range(const ProbDev &P, const PhaseWin &pw, int k,
 // bounds are not monotone.  [ja, jb) as phase_window, [ga, gb) as
 // gauss_range.
 template <bool SEC>
-__device__ inline int4 tile_range(const ProbDev &P, const double *phi, int s,
-                                  int t, int k, int2 *side) {
+__device__ inline int4 tile_range(const ProbDev &P, const StepDev &st,
+                                  const double *phi, int s, int t, int k,
+                                  int2 *side) {
 #pragma clang fp contract(off)
     const int i0 = t * kTile, i1 = min(i0 + kTile, P.N);
     const double xa = P.x[i0], xb = P.x[i1 - 1];
-    const PhaseWin pw = phase_window<SEC>(P, phi + (size_t)s * P.D * P.K, k, xa, xb);
+    const PhaseWin pw = phase_window<SEC>(P, phi + (size_t)s * P.D * P.K, k, i0, i1,
+                                          st.lo + (size_t)s * P.T,
+                                          st.hi + (size_t)s * P.T);
     const int2 g = gauss_range<SEC>(P, pw, k, xa, xb);
     if (side) {
         const int jr = first_centre_above(P.pos, g.x, g.y, pw.mu, xa);
@@ -1123,7 +1153,8 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
                             : nullptr;
     const double *ph = st.phi + (size_t)s * P.D * K;
     const double xref = P.x[min(i0 + kTile / 2, P.N - 1)];   // the tile's reference
-    const double xa = P.x[i0], xb = P.x[min(i0 + kTile, P.N) - 1];
+    const int i1 = min(i0 + kTile, P.N);
+    const double xa = P.x[i0], xb = P.x[i1 - 1];
     SegPeaks sp;
     sp.pt = as_const(ptt);
     sp.inten = as_const(P.inten);
@@ -1153,7 +1184,7 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
         if (tid < nk) {
             cst = pkv[c0 + tid];
             if (ASYM) iw2r = pkrv[c0 + tid];
-            pw = phase_window<SEC>(P, ph, c0 + tid, xa, xb);
+            pw = phase_window<SEC>(P, ph, c0 + tid, i0, i1, wlo, whi);
             gr = gauss_range<SEC>(P, pw, c0 + tid, xa, xb);
         }
         const int cnt = pw.jb - pw.ja, cg = gr.y - gr.x;
@@ -1178,15 +1209,21 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
             const float iw2 = cst.x, aG = cst.y, aL = cst.z, mu = cst.w;
             // The tile-relative centre comes from the FP64 position (as the
             // per-tile table is formed), the window from the window step's
-            // own bounds and grid search, and the side of an asymmetric peak
-            // from the predicates of the tile plan's side searches.
+            // own bounds and grid search (constant width), and the side of
+            // an asymmetric peak from the predicates of the tile plan's side
+            // searches.
             for (int q = 0; q < cnt; ++q) {
                 const int j = pw.ja + q;
                 const double pj = P.pos[j];
                 const float I = SEC ? psec[4 * j + 1] : P.inten[j];
                 const float c = SEC ? psec[4 * j] : 1.f;
-                const double2 ab = window_bounds<SEC>(P, pj, pw.mu, pw.w, pw.alpha);
-                const GridProbe gp = grid_probe(P.x, P.N, P.x0, P.inv_dx, ab.x, ab.y);
+                // (under the sec law the window step's own windows: forming
+                // them here would take a cosine per record)
+                GridProbe gp{};
+                if (!SEC) {
+                    const double2 ab = window_bounds<SEC>(P, pj, pw.mu, pw.w, pw.alpha);
+                    gp = grid_probe(P.x, P.N, P.x0, P.inv_dx, ab.x, ab.y);
+                }
                 float alo = iw2 * c, ahi = alo;
                 if (ASYM) {
                     // centre at or below the tile's first point: the tile
@@ -1202,7 +1239,7 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
                                              (j < gr.x ? j - pw.ja : q - cg);
                 sm.rec[slot] = make_float4((float)(pj - xref) + mu, alo, I * aL,
                                            gauss ? I * aG : 0.f);
-                const int2 wnd = grid_finish(P.x, P.N, gp);
+                const int2 wnd = SEC ? make_int2(wlo[j], whi[j]) : grid_finish(P.x, P.N, gp);
                 WinRec2<ASYM> w2;
                 w2.lo = wnd.x;
                 w2.hi = wnd.y < wnd.x ? wnd.x : wnd.y;
@@ -1242,7 +1279,7 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
         for (int kl = n_fit + wv; kl < nk; kl += kWaves) {
             const int k = c0 + kl;
             int2 rk2 = make_int2(0, 0);
-            const int4 rk = tile_range<SEC>(P, st.phi, s, t, k, ASYM ? &rk2 : nullptr);
+            const int4 rk = tile_range<SEC>(P, st, st.phi, s, t, k, ASYM ? &rk2 : nullptr);
             win_phase_global<ASYM, SEC>(sp, rk, rk2, pkv[k], ASYM ? pkrv[k] : 0.f,
                                         u, idx, sig);
         }

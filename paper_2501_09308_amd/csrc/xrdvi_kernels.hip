@@ -101,14 +101,18 @@ __global__ __launch_bounds__(kWideWaves * kWave) void k_fused_wide(ProbDev P, St
 }
 
 // a3 + a4 (windowed): forward tile over its staged peak records; grid
-// (ntiles, S), kBlock threads, blocks ordered by XCD.  The register budget
-// is held to the occupancy the staging space allows (six blocks per CU, four
-// with asymmetric records; the sec-law variants are left unbounded).
+// (ntiles, S), kBlock threads, blocks ordered by XCD (constant width).  The
+// register budget is held to the occupancy the staging space allows (six
+// blocks per CU, four with asymmetric records; the sec-law variants are
+// left unbounded).
 template <bool ASYM, bool SEC>
 __global__ __launch_bounds__(kBlock, SEC ? 1 : (ASYM ? 4 : 6)) void k_win(ProbDev P, StepDev st,
                                                 float *f_out) {
     __shared__ WinSmem<ASYM> sm;
-    const int2 ts = xcd_tile_sample(P.ntiles, st.S);
+    // the sec-law variant reads per-sample window and peak records, which
+    // the default order (tile fastest) keeps to a few samples per L2
+    const int2 ts = SEC ? make_int2(blockIdx.x, blockIdx.y)
+                        : xcd_tile_sample(P.ntiles, st.S);
     win_tile<ASYM, SEC>(P, st, ts.x, ts.y, f_out, sm);
 }
 

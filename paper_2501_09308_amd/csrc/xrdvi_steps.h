@@ -127,10 +127,10 @@ __device__ inline void plan_elem(const ProbDev &P, const StepDev &st,
     const int t = (int)(st_idx % P.ntiles), s = (int)(st_idx / P.ntiles);
     if (P.D == 5) {
         int2 side;
-        st.rng[g] = tile_range<SEC>(P, phi, s, t, k, &side);
+        st.rng[g] = tile_range<SEC>(P, st, phi, s, t, k, &side);
         st.rng2[g] = side;
     } else {
-        st.rng[g] = tile_range<SEC>(P, phi, s, t, k, nullptr);
+        st.rng[g] = tile_range<SEC>(P, st, phi, s, t, k, nullptr);
     }
 }
 
