@@ -1398,10 +1398,9 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
     const double mu = ph[K + k];
     const float iw2 = (float)(2.0 / ph[2 * K + k]);
     const float iw2r = ASYM ? asym_iw2(ph[2 * K + k], ph[4 * K + k]) : iw2;
-    // bounded buffer views of the residual and the grid: 32-bit offsets,
-    // and reads past the end return 0
-    const __amdgpu_buffer_rsrc_t rres_rs = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(st.rres + (size_t)s * P.N), (short)0, P.N * 4, kBufferFlags);
+    // bounded buffer views of the residual (one per peak, below) and the
+    // grid: 32-bit offsets, and reads past the end return 0
+    const float *rres_s = st.rres + (size_t)s * P.N;
     const __amdgpu_buffer_rsrc_t x_rs = __builtin_amdgcn_make_buffer_rsrc(
         (void *)P.x, (short)0, P.N * 8, kBufferFlags);
     cptr<int> wlo = as_const(st.lo + (size_t)s * P.T);
@@ -1440,20 +1439,24 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
             rho[q] = pos[jj] + mu;
             span = max(span, len[q]);
         }
+        // each peak's residuals through a buffer view that ends with its
+        // window: lanes past the window read 0 and so weigh their point by 0
+        __amdgpu_buffer_rsrc_t rq[kAdjPeaks];
+#pragma unroll
+        for (int q = 0; q < kAdjPeaks; ++q)
+            rq[q] = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(rres_s + lo[q]), (short)0, len[q] * 4, kBufferFlags);
         for (int c = 0; c < span; c += kWave) {
             float R[kAdjPeaks], rv[kAdjPeaks];
             double d[kAdjPeaks], xv[kAdjPeaks];
-            bool valid[kAdjPeaks];
 #pragma unroll
             for (int q = 0; q < kAdjPeaks; ++q) {
-                valid[q] = c + lane < len[q];
-                // every lane loads; lanes outside the window weigh their
-                // point by 0, and points past the grid's end (a window ending
-                // at N, or lo = N for an empty one) read 0 from the bounded
-                // buffer loads
+                // every lane loads; points past the grid's end (a window
+                // ending at N, or lo = N for an empty one) read 0 from the
+                // bounded grid view, and their residual is 0
                 const int ii = lo[q] + c + lane;
                 rv[q] = __uint_as_float(
-                    __builtin_amdgcn_raw_buffer_load_b32(rres_rs, ii * 4, 0, 0));
+                    __builtin_amdgcn_raw_buffer_load_b32(rq[q], (c + lane) * 4, 0, 0));
                 xv[q] = __builtin_bit_cast(
                     double, __builtin_amdgcn_raw_buffer_load_b64(x_rs, ii * 8, 0, 0));
             }
@@ -1462,7 +1465,7 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int q = 0; q < kAdjPeaks; ++q) {
-                R[q] = rv[q] * (valid[q] ? I[q] : 0.f);
+                R[q] = rv[q] * I[q];
                 d[q] = xv[q] - rho[q];
             }
             AdjPt pt[kAdjPeaks];

@@ -1,7 +1,8 @@
 """Edge cases of the HIP path against the FP64 oracle: one phase with one
-peak, ragged candidate lists with empty phases and zero-intensity peaks,
-peaks outside the grid, a one-point grid, the largest sample count, and a
-window wider than the grid (which must equal the dense sum)."""
+peak, ragged candidate lists with empty phases and zero-intensity peaks
+(constant width and sec law), peaks outside the grid, a one-point grid
+(dense and windowed), the largest sample count, and a window wider than the
+grid (which must equal the dense sum)."""
 import numpy as np
 import pytest
 
@@ -76,9 +77,30 @@ def test_one_phase_one_peak(c):
     _check(prob, W.poisson_counts(f, 3), 7, 4, c)
 
 
-def test_one_point_grid():
-    prob, y = _ragged(41, N=1)
-    _check(prob, np.maximum(y, 60.0), 3, 42, 0.0)
+@pytest.mark.parametrize("c", [0.0, 4.0])
+def test_one_point_grid(c):
+    prob, y = _ragged(41, N=1, c=c)
+    _check(prob, np.maximum(y, 60.0), 3, 42, c)
+
+
+@pytest.mark.parametrize("c", [0.0, 6.0])
+def test_ragged_candidates_with_empty_phases_sec_law(c):
+    # the sec-law searches run over the window step's index arrays, and
+    # empty phases and peaks off the grid must not disturb them
+    prob, y = _ragged(71, c=c)
+    ctx = context()
+    P = X.Problem.from_workload(ctx, prob, y, cutoff=c, width_law="sec")
+    S = 4
+    loc, ls = W.random_params(prob.K, 72, (y - prob.bg).max())
+    eps = W.eps_draw(S, prob.K, 73)
+    tape = X.Tape(ctx, P, S)
+    e, ll = X.xrdvi_elbo_fwd(ctx, P, tape, dev(loc), dev(ls), eps=dev(eps))
+    gl, gs = X.xrdvi_elbo_bwd(ctx, tape)
+    re, rll, rgl, rgs = oracle.elbo_sec(prob, y, loc, ls, eps)
+    assert abs(e.item() - re) <= ELBO_RTOL * abs(re)
+    np.testing.assert_allclose(ll.cpu().numpy(), rll, rtol=ELBO_RTOL)
+    g = np.concatenate([gl.cpu().numpy().ravel(), gs.cpu().numpy().ravel()])
+    assert rel_l2(g, np.concatenate([rgl.ravel(), rgs.ravel()])) <= GRAD_RTOL
 
 
 def test_largest_sample_count():
