@@ -1,0 +1,94 @@
+"""A seeded sweep of random configurations of the HIP path against the FP64
+oracle: grid origin, spacing and length, candidate counts (ragged), peak
+widths, window cutoff (dense, narrow, wide, wider than most peaks' reach),
+sample count, symmetric or asymmetric peaks, and the constant or sec width
+law.  Each case checks the window plan bit for bit (windowed cases), the
+profile (max relative 2e-5), the ELBO and the per-sample log-likelihoods
+(relative 1e-6) and the gradient (relative L2 1e-4), the bars of the
+targeted parity tests, on shapes those do not pick."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_09308_amd import workloads as W
+from paper_2501_09308_amd import xrdvi as X
+
+from gpu_common import context, dev, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+PROFILE_RTOL = 2e-5
+ELBO_RTOL = 1e-6
+GRAD_RTOL = 1e-4
+CASES = 28        # the last four with 200-400 candidates (the windowed tile's
+                  # staging space overflows into its global-memory path)
+
+
+def _config(seed):
+    rng = np.random.default_rng(9100 + seed)
+    step = float(rng.choice([0.005, 0.01, 0.02, 0.04]))
+    x0 = float(rng.uniform(5.0, 60.0))
+    # keep 2-theta below 165 deg (the sec law's widths stay finite)
+    N = int(min(rng.integers(50, 4000), (165.0 - x0) / step))
+    big = seed >= CASES - 4
+    K = int(rng.integers(200, 400) if big else rng.integers(1, 120))
+    m_hi = int(rng.integers(40, 80) if big else rng.integers(1, 50))
+    cfg = dict(x0=x0, step=step, N=N, K=K, M_range=(1, m_hi),
+               n_true=min(K, 3), S=1, cutoff=0.0,
+               fwhm=(0.02, float(rng.choice([0.05, 0.2, 0.5]))))
+    c = float(rng.choice([8.0, 30.0] if big else [0.0, 1.5, 4.0, 8.0, 30.0]))
+    S = int(rng.choice([1, 2, 5, 8]))
+    D = int(rng.choice([4, 5]))
+    sec = bool(rng.integers(0, 2))
+    return cfg, c, S, D, sec
+
+
+def _oracle(sec, D):
+    if sec:
+        return oracle.profile_sec, oracle.windows_sec, oracle.elbo_sec
+    if D == 5:
+        return oracle.profile_asym, oracle.windows_asym, oracle.elbo_asym
+    return oracle.profile, oracle.windows, oracle.elbo
+
+
+@pytest.mark.parametrize("seed", range(CASES))
+def test_random_configuration_matches_oracle(seed):
+    cfg, c, S, D, sec = _config(seed)
+    prob = W.make_problem(cfg, seed)
+    prof, wins, elbo = _oracle(sec, D)
+    truth = prob.phi_true
+    if D == 5:
+        truth = np.concatenate([truth, W.random_alpha(prob.K, 1, seed)])
+    fstar = prof(prob.x, prob.bg, prob.peak_off, prob.peak_pos, prob.peak_int,
+                 0.0, truth)[0]
+    y = W.poisson_counts(fstar, seed + 1)
+    prob.cutoff = c
+    print(f"\nsweep {seed}: N={prob.N} step={cfg['step']} K={prob.K} "
+          f"T={prob.total_peaks} c={c} S={S} D={D} sec={sec}", flush=True)
+    ctx = context()
+    P = X.Problem.from_workload(ctx, prob, y, cutoff=c, asymmetric=D == 5,
+                                width_law="sec" if sec else 0)
+    # the forward at scattered latents, and the window plan
+    phi = W.random_phi(prob.K, S, seed + 2)
+    if D == 5:
+        phi = np.concatenate([phi, W.random_alpha(prob.K, S, seed + 3)[:, None, :]],
+                             axis=1)
+    f = X.xrdvi_profile(ctx, P, dev(phi)).cpu().numpy()
+    ref = prof(prob.x, prob.bg, prob.peak_off, prob.peak_pos, prob.peak_int, c, phi)
+    assert np.max(np.abs(f - ref) / ref) <= PROFILE_RTOL
+    if c > 0.0:
+        lo, hi = X.xrdvi_window_plan(ctx, P, dev(phi))
+        rlo, rhi = wins(prob.x, prob.peak_off, prob.peak_pos, c, phi)
+        assert np.array_equal(lo.cpu().numpy(), rlo)
+        assert np.array_equal(hi.cpu().numpy(), rhi)
+    # the ELBO and its gradient
+    loc, ls = W.random_params(prob.K, seed + 4, float((y - prob.bg).max()), D=D)
+    eps = W.eps_draw(S, prob.K, seed + 5, D=D)
+    tape = X.Tape(ctx, P, S)
+    e, ll = X.xrdvi_elbo_fwd(ctx, P, tape, dev(loc), dev(ls), eps=dev(eps))
+    gl, gs = X.xrdvi_elbo_bwd(ctx, tape)
+    re, rll, rgl, rgs = elbo(prob, y, loc, ls, eps)
+    assert abs(e.item() - re) <= ELBO_RTOL * abs(re)
+    np.testing.assert_allclose(ll.cpu().numpy(), rll, rtol=ELBO_RTOL)
+    g = np.concatenate([gl.cpu().numpy().ravel(), gs.cpu().numpy().ravel()])
+    assert rel_l2(g, np.concatenate([rgl.ravel(), rgs.ravel()])) <= GRAD_RTOL
