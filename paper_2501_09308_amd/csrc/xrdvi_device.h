@@ -204,11 +204,10 @@ __device__ __forceinline__ float asym_iw2(double w, double alpha) {
 
 // ---- window plan ---------------------------------------------------------
 
-// Grid searches.  The grid is ascending and usually close to uniform, so
-// the search starts at the index a uniform grid would give, walks a few
-// points checking the true values, and only falls back to bisection of the
-// remaining bracket when the walk does not settle: the result is the exact
-// bound for any ascending grid.
+// Grid searches.  The grid is ascending and usually close to uniform, so a
+// search starts at the index a uniform grid would give and checks the true
+// values there (grid_range below); the result is the exact bound for any
+// ascending grid.
 
 // Index guess for value v on a grid starting at x0 with inv_dx points per
 // unit (clamped to [0, n]; NaN gives 0).
@@ -219,33 +218,6 @@ __host__ __device__ inline int grid_guess(double x0, double inv_dx, int n,
     if (!(g < (double)n)) return n;
     return (int)g;
 }
-
-// First i with x[i] >= v (STRICT = false) or x[i] > v (STRICT = true).
-template <bool STRICT>
-__host__ __device__ inline int grid_bound(const double *x, int n, double x0,
-                                          double inv_dx, double v) {
-    auto before = [&](int i) { return STRICT ? x[i] <= v : x[i] < v; };
-    int i = grid_guess(x0, inv_dx, n, v);
-    // the bound lies in [lo, hi]: i is a candidate, move towards it
-    int lo = 0, hi = n;
-    for (int step = 0; step < 4; ++step) {
-        if (i > 0 && !before(i - 1)) {          // bound is at or left of i - 1
-            hi = i - 1;
-            --i;
-        } else if (i < n && before(i)) {        // bound is right of i
-            lo = i + 1;
-            ++i;
-        } else {
-            return i;                           // x[i-1] before v, x[i] not
-        }
-    }
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (before(mid)) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
 
 // Batched searches.  A search from a good guess costs one round trip to
 // memory when the entries around the guess are loaded together: a probe
@@ -321,9 +293,9 @@ __host__ __device__ inline int probe_result(const T *v, int a, int b,
 }
 
 // Grid range [lo, hi) of the points with va <= x_i <= vb (lo = first i with
-// x[i] >= va, hi = first i with x[i] > vb; the comparisons of grid_bound,
-// so NaN gives 0), each bound from a two-point probe at the uniform-grid
-// guess.  grid_probe issues both probes, grid_finish reads the bounds off
+// x[i] >= va, hi = first i with x[i] > vb; both written as negated "before"
+// tests, so a NaN bound gives 0), each bound from a two-point probe at the
+// uniform-grid guess.  grid_probe issues both probes, grid_finish reads the bounds off
 // them, so that the probes of several ranges can be in flight together.
 struct GridProbe {
     Probe<2, double> a, b;
