@@ -122,7 +122,8 @@ __global__ __launch_bounds__(256) void kb_plan(const SlotDev *tab,
 template <bool WIN, bool ASYM, bool SEC>
 __global__ __launch_bounds__(kBlock) void kb_fused(const SlotDev *tab,
                                                    const SchedDev *sch) {
-    using Smem = typename std::conditional<WIN, WinSmem<ASYM>, FusedSmem>::type;
+    using Smem = typename std::conditional<WIN, WinSmem<ASYM, kWinPeaksBatched>,
+                                           FusedSmem>::type;
     __shared__ PrefixSmem ps;
     __shared__ Smem sm;
     load_prefix(sch, fused_kind(WIN, ASYM, SEC), ps);

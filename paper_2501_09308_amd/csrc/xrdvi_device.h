@@ -1006,7 +1006,12 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
 // fit the staging space (they come last in the chunk) are evaluated from
 // global memory, phase by phase.
 constexpr int kWinChunk = kBlock;   // phases staged at a time (one per thread)
-constexpr int kWinPeaks = 1024;     // staged peak records per chunk
+// Staged peak records per chunk: 768 (21 KB of LDS, seven blocks per CU)
+// for the single-analysis forward; 1024 for the batched one, whose registers
+// already hold it to four blocks per CU and whose larger analyses would
+// otherwise spill more phases to the global-memory path.
+constexpr int kWinPeaks = 768;
+constexpr int kWinPeaksBatched = 1024;
 
 // Second word of a staged record: the window, and for asymmetric peaks the
 // scale above the centre.
@@ -1022,10 +1027,11 @@ struct WinRec2<true> {
     __device__ __forceinline__ float ahi(float) const { return ah; }
 };
 
-template <bool ASYM>
+template <bool ASYM, int CAP = kWinPeaks>
 struct WinSmem {
-    float4 rec[kWinPeaks];          // (centre, 2c/(Aw) below, amp L, amp G)
-    WinRec2<ASYM> rec2[kWinPeaks];  // (lo, hi[, 2c/(alpha w)])
+    static constexpr int kCap = CAP;
+    float4 rec[CAP];                // (centre, 2c/(Aw) below, amp L, amp G)
+    WinRec2<ASYM> rec2[CAP];        // (lo, hi[, 2c/(alpha w)])
     int wmax[kWaves], wmaxn[kWaves], wcnt[kWaves], wcntg[kWaves];
     float sig[kWaves][kTile];
     float rres[kTile];
@@ -1108,9 +1114,10 @@ __device__ __forceinline__ int2 xcd_tile_sample(int ntiles, int S) {
     return make_int2(q / S, q % S);
 }
 
-template <bool ASYM, bool SEC>
+template <bool ASYM, bool SEC, typename SM>
 __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
-                         float *f_out, WinSmem<ASYM> &sm) {
+                         float *f_out, SM &sm) {
+    constexpr int kCap = SM::kCap;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -1176,7 +1183,7 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
         // records of the phases that fit (a prefix of the chunk: incl grows
         // with the phase index).  Records with a Gaussian fill the list from
         // the front, the others from the back, each in phase and peak order.
-        const bool fits = tid < nk && incl <= kWinPeaks;
+        const bool fits = tid < nk && incl <= kCap;
         if (fits) {
             const float iw2 = cst.x, aG = cst.y, aL = cst.z, mu = cst.w;
             // The tile-relative centre comes from the FP64 position (as the
@@ -1207,7 +1214,7 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
                 }
                 const bool gauss = j >= gr.x && j < gr.y;
                 const int slot = gauss ? exclg + (j - gr.x)
-                                       : kWinPeaks - 1 - excln -
+                                       : kCap - 1 - excln -
                                              (j < gr.x ? j - pw.ja : q - cg);
                 sm.rec[slot] = make_float4((float)(pj - xref) + mu, alo, I * aL,
                                            gauss ? I * aG : 0.f);
@@ -1245,8 +1252,8 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
             win_record<ASYM, true>(sm.rec[f], sm.rec2[f], u, idx, sig);
 #pragma unroll 2
         for (int f = wv; f < n_n; f += kWaves)
-            win_record<ASYM, false>(sm.rec[kWinPeaks - 1 - f],
-                                    sm.rec2[kWinPeaks - 1 - f], u, idx, sig);
+            win_record<ASYM, false>(sm.rec[kCap - 1 - f],
+                                    sm.rec2[kCap - 1 - f], u, idx, sig);
         // phases that did not fit (every lane finds the same ranges)
         for (int kl = n_fit + wv; kl < nk; kl += kWaves) {
             const int k = c0 + kl;

@@ -102,11 +102,11 @@ __global__ __launch_bounds__(kWideWaves * kWave) void k_fused_wide(ProbDev P, St
 
 // a3 + a4 (windowed): forward tile over its staged peak records; grid
 // (ntiles, S), kBlock threads, blocks ordered by XCD (constant width).  The
-// register budget is held to the occupancy the staging space allows (six
-// blocks per CU, four with asymmetric records; the sec-law variants are
+// register budget is held to the occupancy the staging space allows (seven
+// blocks per CU, five with asymmetric records; the sec-law variants are
 // left unbounded).
 template <bool ASYM, bool SEC>
-__global__ __launch_bounds__(kBlock, SEC ? 1 : (ASYM ? 4 : 6)) void k_win(ProbDev P, StepDev st,
+__global__ __launch_bounds__(kBlock, SEC ? 1 : (ASYM ? 5 : 7)) void k_win(ProbDev P, StepDev st,
                                                 float *f_out) {
     __shared__ WinSmem<ASYM> sm;
     // the sec-law variant reads per-sample window and peak records, which
