@@ -422,6 +422,41 @@ def test_adam_first_step_is_signed_lr(orc):
     np.testing.assert_allclose(th, [1.01, -2.01, 0.5], rtol=1e-6)
 
 
+def test_adam_constant_gradient_moves_lr_per_step(orc):
+    # Kingma & Ba, Algorithm 1: from zero moments under a constant gradient
+    # g, m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the bias-corrected
+    # moments are exactly g and g^2 at every t and each step moves theta by
+    # lr g / (|g| + eps).  A correction by (1 - b1) instead of (1 - b1^t)
+    # would shrink the moves after the first.
+    g = np.array([3.0, -0.25, 1e-3, -40.0])
+    th = np.array([0.5, -1.0, 2.0, 0.0]); th0 = th.copy()
+    m1 = np.zeros(4); m2 = np.zeros(4)
+    lr, e = 0.01, 1e-8
+    for t in range(1, 11):
+        orc.adam(th, m1, m2, g, t, lr=lr, e=e)
+        np.testing.assert_allclose(th, th0 + t * lr * g / (np.abs(g) + e),
+                                   rtol=1e-12, atol=1e-14)
+
+
+def test_adam_two_steps_with_a_sign_change(orc):
+    # b1 = 0.9, b2 = 0.999, gradients g1 then g2, worked by hand:
+    #   m2 = 0.09 g1 + 0.1 g2,  v2 = 0.000999 g1^2 + 0.001 g2^2,
+    #   bias corrections 1 - 0.9^2 = 0.19 and 1 - 0.999^2 = 0.001999.
+    # (g1, g2) = (1, -1):  m^ = -0.01 / 0.19 = -1/19, v^ = 1, so the two
+    #                      steps move lr (1 - 1/19) = lr 18/19;
+    # (g1, g2) = (2, -0.5): m^ = 0.13 / 0.19 = 13/19,
+    #                      v^ = 0.004246 / 0.001999 = 4246/1999.
+    lr = 0.01
+    th = np.zeros(2); m1 = np.zeros(2); m2 = np.zeros(2)
+    orc.adam(th, m1, m2, np.array([1.0, 2.0]), 1, lr=lr, e=0.0)
+    np.testing.assert_allclose(th, [lr, lr], rtol=1e-13)
+    orc.adam(th, m1, m2, np.array([-1.0, -0.5]), 2, lr=lr, e=0.0)
+    want = [lr * 18.0 / 19.0, lr + lr * (13.0 / 19.0) / np.sqrt(4246.0 / 1999.0)]
+    np.testing.assert_allclose(th, want, rtol=1e-12)
+    np.testing.assert_allclose(m1, [-0.01, 0.13], rtol=1e-12)
+    np.testing.assert_allclose(m2, [0.001999, 0.004246], rtol=1e-12)
+
+
 def test_gradient_central_differences_at_stress200_scale(orc):
     # 200 phases x 60 peaks over 10-80 deg (the stress200 candidate set, on a
     # 0.07 deg grid to keep the oracle fast), S = 2, dense: 32 random
