@@ -103,7 +103,7 @@ StepDev carve_step(void *base, const StepShape &sh) {
 
 // Device layout of a prepared problem, in 256-byte aligned pieces.
 struct ProblemLayout {
-    size_t x, y, bg, lgy, u, off, ph, pos, inten, pt, perm, ptab, total;
+    size_t x, y, bg, lgy, u, ul, off, ph, pos, inten, pt, ptl, perm, ptab, total;
 };
 
 static ProblemLayout problem_layout(int N, int K, int T) {
@@ -114,9 +114,11 @@ static ProblemLayout problem_layout(int N, int K, int T) {
     auto slot = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
     L.x = slot(8 * (size_t)N); L.y = slot(8 * (size_t)N);
     L.bg = slot(8 * (size_t)N); L.lgy = slot(8 * (size_t)N);
-    L.u = slot(4 * (size_t)nt * kTile); L.off = slot(4 * (size_t)(K + 1));
+    L.u = slot(4 * (size_t)nt * kTile); L.ul = slot(4 * (size_t)nt * kTile);
+    L.off = slot(4 * (size_t)(K + 1));
     L.ph = slot(4 * T1); L.pos = slot(8 * T1); L.inten = slot(4 * T1);
-    L.pt = slot(4 * (size_t)nt * T1); L.perm = slot(4 * T1);
+    L.pt = slot(4 * (size_t)nt * T1); L.ptl = slot(4 * (size_t)nt * T1);
+    L.perm = slot(4 * T1);
     L.ptab = slot(4 * (size_t)K * (kTabBuckets + 1));
     L.total = o;
     return L;
@@ -199,17 +201,20 @@ hipError_t upload_problem(const xrdvi_problem_desc &d, double lambda,
     P.bg = (const double *)(base + L.bg);
     P.lgy = (const double *)(base + L.lgy);
     P.u = (const float *)(base + L.u);
+    P.ul = (const float *)(base + L.ul);
     P.off = (const int *)(base + L.off);
     P.phase = (const int *)(base + L.ph);
     P.pos = (const double *)(base + L.pos);
     P.inten = (const float *)(base + L.inten);
     P.pt = (const float *)(base + L.pt);
+    P.ptl = (const float *)(base + L.ptl);
     P.ptab = (const int *)(base + L.ptab);
     P.tab_x0 = tab_x0;
     P.tab_inv = tab_inv;
     if (perm_out) *perm_out = (int *)(base + L.perm);
     return launch_prepare(P, (double *)(base + L.lgy), (float *)(base + L.u),
-                          (float *)(base + L.pt), stream);
+                          (float *)(base + L.ul), (float *)(base + L.pt),
+                          (float *)(base + L.ptl), stream);
 }
 
 }  // namespace xrdvi

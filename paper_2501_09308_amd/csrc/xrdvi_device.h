@@ -73,11 +73,15 @@ struct ProbDev {
     double x0, inv_dx;                // x[0] and (N - 1) / (x[N-1] - x[0])
                                       // (0 for N = 1): grid-search guesses
     const float *u;                   // [ntiles * kTile] x_i - xref_tile
+                                      // (FP32, rounded)
+    const float *ul;                  // [ntiles * kTile] its rounding
+                                      // error: (x_i - xref) - u_i in FP32
     const int *off;                   // [K + 1]
     const int *phase;                 // [T] phase of each peak
     const double *pos;                // [T]
     const float *inten;               // [T]
     const float *pt;                  // [ntiles][T] p_j - xref_tile
+    const float *ptl;                 // [ntiles][T] its rounding error
     // position index of each phase's sorted peaks: ptab[k][b] is the first
     // peak j of phase k with pos[j] >= tab_x0 + b / tab_inv (b = 0 ..
     // kTabBuckets), a starting guess for searches over positions
@@ -608,28 +612,31 @@ struct PeakMask {
     }
 };
 
-// One peak as a segment loop sees it: tile-relative position, intensity,
+// One peak as a segment loop sees it: tile-relative position (and, for the
+// peaks near the tile, the rounding error of that position), intensity,
 // (windowed mode) its grid window [lo, hi) and, with the sec width law,
 // c = |cos theta| and tw = tan(theta) (pi/360) w (the intensity is then
 // I c).
 struct PeakRec {
-    float pt, I;
+    float pt, ptl, I;
     int lo, hi;
     float c, tw;
 };
 
 struct SegPeaks {
     cptr<float> pt;       // tile-relative positions
+    cptr<float> ptl;      // their rounding errors
     cptr<float> inten;
     cptr<int> wlo, whi;   // windows (WIN)
     cptr<float> sec;      // per-sample sec-law records, 4 floats each (SEC)
     // scalar loads (unused fields are never loaded)
-    template <bool SEC>
+    template <bool SEC, bool NEAR>
     __device__ __forceinline__ PeakRec rec(int j) const {
+        const float l = NEAR ? ptl[j] : 0.f;
         if (SEC)
-            return PeakRec{pt[j], sec[4 * j + 1], wlo[j], whi[j], sec[4 * j],
+            return PeakRec{pt[j], l, sec[4 * j + 1], wlo[j], whi[j], sec[4 * j],
                            sec[4 * j + 2]};
-        return PeakRec{pt[j], inten[j], wlo[j], whi[j], 1.f, 0.f};
+        return PeakRec{pt[j], l, inten[j], wlo[j], whi[j], 1.f, 0.f};
     }
 };
 
@@ -637,44 +644,81 @@ struct SegPeaks {
 // symmetric), above them, or on both sides (chosen per point).
 enum { kBelow = 0, kAbove = 1, kBoth = 2 };
 
-// q2 = 2 (x - rho) / (A w) of point p for peak position ptj.
-template <int SIDE>
-__device__ __forceinline__ float seg_q2(float ptj, float iw2, float iw2r,
-                                        float uq, float uqr) {
-    if (SIDE == kBelow) return fmaf(-ptj, iw2, uq);
-    if (SIDE == kAbove) return fmaf(-ptj, iw2r, uqr);
-    const float ql = fmaf(-ptj, iw2, uq);
-    const float qr = fmaf(-ptj, iw2r, uqr);
-    return ql >= 0.f ? qr : ql;
+// The lane's points as one phase's segment loops see them (mu: the phase's
+// FP32 shift; iw2, iw2r: 2 / (A w) below and above the centre).  Two forms
+// of q2 = 2 (x - rho) / (A w) for a peak at tile-relative position pt:
+//   far:  q2 = fma(-pt, iw2, uq),                   uq  = (u - mu) iw2,
+//   near: q2 = fma(u - pt, iw2, fma(-ptl, iw2, uql)), uql = (ul - mu) iw2.
+// The far form carries the rounding of u, pt and uq, an absolute error in
+// x - rho of a few 1e-8 times the tile's extent in degrees: harmless where
+// q2 is large, but near the centre of a narrow peak, where the Gaussian is
+// steep, it would set the profile's error.  The near form subtracts the
+// rounded parts first (u - pt is exact or carries only its own relative
+// rounding) and adds the small rounding errors ul and ptl separately, so
+// that x - rho keeps a relative error of a few units of FP32 rounding.
+// Peaks whose Gaussian reaches the tile take the near form (two more VALU
+// operations per point), the others the far form.
+struct PhasePts {
+    float uq[kPPL], uqr[kPPL], uql[kPPL], uqlr[kPPL];
+    __device__ __forceinline__ void set(const float (&u)[kPPL],
+                                        const float (&ul)[kPPL], float mu,
+                                        float iw2, float iw2r, bool asym) {
+#pragma unroll
+        for (int p = 0; p < kPPL; ++p) {
+            const float um = u[p] - mu, ulm = ul[p] - mu;
+            uq[p] = um * iw2;
+            uql[p] = ulm * iw2;
+            uqr[p] = asym ? um * iw2r : uq[p];
+            uqlr[p] = asym ? ulm * iw2r : uql[p];
+        }
+    }
+};
+
+// q2 of point p for peak r, and whether the point lies at or above the
+// centre (the side of an asymmetric peak).  Sec law: the constant-width q2
+// scaled by the peak's c.
+struct SegQ {
+    float q2;
+    bool up;
+};
+template <int SIDE, bool NEAR, bool SEC>
+__device__ __forceinline__ SegQ seg_q(const PeakRec &r, float u,
+                                      const PhasePts &pp, int p, float iw2,
+                                      float iw2r) {
+    float ql = 0.f, qr = 0.f;
+    if (NEAR) {
+        const float d = u - r.pt;
+        if (SIDE != kAbove) ql = fmaf(d, iw2, fmaf(-r.ptl, iw2, pp.uql[p]));
+        if (SIDE != kBelow) qr = fmaf(d, iw2r, fmaf(-r.ptl, iw2r, pp.uqlr[p]));
+    } else {
+        if (SIDE != kAbove) ql = fmaf(-r.pt, iw2, pp.uq[p]);
+        if (SIDE != kBelow) qr = fmaf(-r.pt, iw2r, pp.uqr[p]);
+    }
+    const bool up = SIDE == kAbove || (SIDE == kBoth && ql >= 0.f);
+    const float q = SIDE == kBelow ? ql : (SIDE == kAbove ? qr : (up ? qr : ql));
+    return SegQ{SEC ? r.c * q : q, up};
 }
 
-// Sec law: q2 = c 2 (x - rho) / (A w), the constant-width q2 (one rounding
-// of a fused multiply-add, accurate near the peak) scaled by c.
-template <int SIDE>
-__device__ __forceinline__ float seg_q2_sec(float c, float ptj, float iw2,
-                                            float iw2r, float uq, float uqr) {
-    return c * seg_q2<SIDE>(ptj, iw2, iw2r, uq, uqr);
-}
-
+// Forward terms of the peaks [j0, j1) of one phase: accL += I l, accG += I e
+// (GAUSS) with l = 1 / (1 + q2^2), e = 2^(-q2^2); GAUSS segments take the
+// near form of q2.
 template <bool WIN, bool GAUSS, int SIDE, bool SEC, typename PK>
 __device__ __forceinline__ void fwd_segment(const PK &pk, int j0, int j1,
                                             const int (&idx)[kPPL],
-                                            const float (&uq)[kPPL],
-                                            const float (&uqr)[kPPL],
+                                            const float (&u)[kPPL],
+                                            const PhasePts &pp,
                                             float iw2, float iw2r,
                                             float (&accL)[kPPL],
                                             float (&accG)[kPPL]) {
 #pragma unroll 2
     for (int j = j0; j < j1; ++j) {
-        const PeakRec r = pk.template rec<SEC>(j);
-        const float ptj = r.pt;
+        const PeakRec r = pk.template rec<SEC, GAUSS>(j);
         const float I = r.I;
         PeakMask<WIN> mk;
         if (WIN) { mk.lo = r.lo; mk.hi = r.hi; }
 #pragma unroll
         for (int p = 0; p < kPPL; ++p) {
-            const float q2 = SEC ? seg_q2_sec<SIDE>(r.c, ptj, iw2, iw2r, uq[p], uqr[p])
-                                 : seg_q2<SIDE>(ptj, iw2, iw2r, uq[p], uqr[p]);
+            const float q2 = seg_q<SIDE, GAUSS, SEC>(r, u[p], pp, p, iw2, iw2r).q2;
             const float tt = mk.apply(idx[p], fmaf(q2, q2, 1.0f));
             accL[p] = fmaf(I, rcp_f32(tt), accL[p]);
             if (GAUSS) accG[p] = fmaf(I, exp2_f32(1.0f - tt), accG[p]);
@@ -715,14 +759,13 @@ struct SecW {
 template <bool WIN, bool GAUSS, int SIDE, bool SEC>
 __device__ __forceinline__ void adj_segment(const SegPeaks &pk, int j0, int j1,
                                             const int (&idx)[kPPL],
-                                            const float (&uq)[kPPL],
-                                            const float (&uqr)[kPPL],
+                                            const float (&u)[kPPL],
+                                            const PhasePts &pp,
                                             float iw2, float iw2r, float ka,
                                             Acc6 &lo, Acc6 &hi) {
 #pragma unroll 2
     for (int j = j0; j < j1; ++j) {
-        const PeakRec r = pk.template rec<SEC>(j);
-        const float ptj = r.pt;
+        const PeakRec r = pk.template rec<SEC, GAUSS>(j);
         const float I = r.I;
         SecW wl{0.f, 0.f, 0.f}, wh{0.f, 0.f, 0.f};
         if (SEC) {
@@ -733,8 +776,8 @@ __device__ __forceinline__ void adj_segment(const SegPeaks &pk, int j0, int j1,
         if (WIN) { mk.lo = r.lo; mk.hi = r.hi; }
 #pragma unroll
         for (int p = 0; p < kPPL; ++p) {
-            const float q2 = SEC ? seg_q2_sec<SIDE>(r.c, ptj, iw2, iw2r, uq[p], uqr[p])
-                                 : seg_q2<SIDE>(ptj, iw2, iw2r, uq[p], uqr[p]);
+            const SegQ sq = seg_q<SIDE, GAUSS, SEC>(r, u[p], pp, p, iw2, iw2r);
+            const float q2 = sq.q2;
             const float tt = mk.apply(idx[p], fmaf(q2, q2, 1.0f));
             const float l = rcp_f32(tt);
             const float Il = I * l;
@@ -768,7 +811,7 @@ __device__ __forceinline__ void adj_segment(const SegPeaks &pk, int j0, int j1,
                 }
             } else {
                 const float Ieqq = Ieq * q2;
-                const bool up = fmaf(-ptj, iw2, uq[p]) >= 0.f;
+                const bool up = sq.up;
                 const float fu = up ? 1.f : 0.f;
                 const float fd = 1.f - fu;
                 float m1L, m1G = 0.f;
@@ -886,18 +929,20 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
     }
     SegPeaks sp;
     sp.pt = as_const(P.pt + (size_t)t * P.T);
+    sp.ptl = as_const(P.ptl + (size_t)t * P.T);
     sp.inten = as_const(P.inten);
     sp.wlo = as_const(st.lo + (size_t)s * P.T);
     sp.whi = as_const(st.hi + (size_t)s * P.T);
     sp.sec = SEC ? as_const(reinterpret_cast<const float *>(st.psec + (size_t)s * P.T))
                  : nullptr;
 
-    float u[kPPL];
+    float u[kPPL], ul[kPPL];
     int idx[kPPL];
 #pragma unroll
     for (int p = 0; p < kPPL; ++p) {
         idx[p] = i0 + p * kWave + lane;
         u[p] = P.u[idx[p]];
+        ul[p] = P.ul[idx[p]];
     }
 
     // ---------------- forward: partial signal over this wave's phases
@@ -912,25 +957,25 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
         const float iw2 = in_vgpr(pk[4 * k]);
         const float aG = pk[4 * k + 1], aL = pk[4 * k + 2], mu = pk[4 * k + 3];
         const float iw2r = ASYM ? in_vgpr(pkr[k]) : iw2;
-        float uq[kPPL], uqr[kPPL], accL[kPPL], accG[kPPL];
+        PhasePts pp;
+        pp.set(u, ul, mu, iw2, iw2r, ASYM);
+        float accL[kPPL], accG[kPPL];
 #pragma unroll
         for (int p = 0; p < kPPL; ++p) {
-            uq[p] = (u[p] - mu) * iw2;
-            uqr[p] = ASYM ? (u[p] - mu) * iw2r : uq[p];
             accL[p] = 0.f;
             accG[p] = 0.f;
         }
         if (ASYM) {
             const int jr = rg2[2 * k], jl = rg2[2 * k + 1];
-            fwd_segment<WIN, false, kAbove, SEC>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
-            fwd_segment<WIN, true, kAbove, SEC>(sp, ga, jr, idx, uq, uqr, iw2, iw2r, accL, accG);
-            fwd_segment<WIN, true, kBoth, SEC>(sp, jr, jl, idx, uq, uqr, iw2, iw2r, accL, accG);
-            fwd_segment<WIN, true, kBelow, SEC>(sp, jl, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
-            fwd_segment<WIN, false, kBelow, SEC>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, false, kAbove, SEC>(sp, ja, ga, idx, u, pp, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, true, kAbove, SEC>(sp, ga, jr, idx, u, pp, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, true, kBoth, SEC>(sp, jr, jl, idx, u, pp, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, true, kBelow, SEC>(sp, jl, gb, idx, u, pp, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, false, kBelow, SEC>(sp, gb, jb, idx, u, pp, iw2, iw2r, accL, accG);
         } else {
-            fwd_segment<WIN, false, kBelow, SEC>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
-            fwd_segment<WIN, true, kBelow, SEC>(sp, ga, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
-            fwd_segment<WIN, false, kBelow, SEC>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, false, kBelow, SEC>(sp, ja, ga, idx, u, pp, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, true, kBelow, SEC>(sp, ga, gb, idx, u, pp, iw2, iw2r, accL, accG);
+            fwd_segment<WIN, false, kBelow, SEC>(sp, gb, jb, idx, u, pp, iw2, iw2r, accL, accG);
         }
 #pragma unroll
         for (int p = 0; p < kPPL; ++p)
@@ -962,27 +1007,23 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
         const float iw2 = in_vgpr(pk[4 * k]);
         const float mu = pk[4 * k + 3];
         const float iw2r = ASYM ? in_vgpr(pkr[k]) : iw2;
-        float uq[kPPL], uqr[kPPL];
-#pragma unroll
-        for (int p = 0; p < kPPL; ++p) {
-            uq[p] = (u[p] - mu) * iw2;
-            uqr[p] = ASYM ? (u[p] - mu) * iw2r : uq[p];
-        }
+        PhasePts pp;
+        pp.set(u, ul, mu, iw2, iw2r, ASYM);
         const float ka = ASYM && SEC ? iw2 / iw2r : 1.f;   // alpha
         Acc6 lo, hi;
         lo.zero();
         if (ASYM) {
             hi.zero();
             const int jr = rg2[2 * k], jl = rg2[2 * k + 1];
-            adj_segment<WIN, false, kAbove, SEC>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
-            adj_segment<WIN, true, kAbove, SEC>(sp, ga, jr, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
-            adj_segment<WIN, true, kBoth, SEC>(sp, jr, jl, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
-            adj_segment<WIN, true, kBelow, SEC>(sp, jl, gb, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
-            adj_segment<WIN, false, kBelow, SEC>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
+            adj_segment<WIN, false, kAbove, SEC>(sp, ja, ga, idx, u, pp, iw2, iw2r, ka, lo, hi);
+            adj_segment<WIN, true, kAbove, SEC>(sp, ga, jr, idx, u, pp, iw2, iw2r, ka, lo, hi);
+            adj_segment<WIN, true, kBoth, SEC>(sp, jr, jl, idx, u, pp, iw2, iw2r, ka, lo, hi);
+            adj_segment<WIN, true, kBelow, SEC>(sp, jl, gb, idx, u, pp, iw2, iw2r, ka, lo, hi);
+            adj_segment<WIN, false, kBelow, SEC>(sp, gb, jb, idx, u, pp, iw2, iw2r, ka, lo, hi);
         } else {
-            adj_segment<WIN, false, kBelow, SEC>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
-            adj_segment<WIN, true, kBelow, SEC>(sp, ga, gb, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
-            adj_segment<WIN, false, kBelow, SEC>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, ka, lo, hi);
+            adj_segment<WIN, false, kBelow, SEC>(sp, ja, ga, idx, u, pp, iw2, iw2r, ka, lo, hi);
+            adj_segment<WIN, true, kBelow, SEC>(sp, ga, gb, idx, u, pp, iw2, iw2r, ka, lo, hi);
+            adj_segment<WIN, false, kBelow, SEC>(sp, gb, jb, idx, u, pp, iw2, iw2r, ka, lo, hi);
         }
         store_sums(lo, rres, lane, dst);
         if (ASYM) store_sums(hi, rres, lane, dst + 6);
@@ -1013,25 +1054,60 @@ constexpr int kWinChunk = kBlock;   // phases staged at a time (one per thread)
 constexpr int kWinPeaks = 768;
 constexpr int kWinPeaksBatched = 1024;
 
-// Second word of a staged record: the window, and for asymmetric peaks the
-// scale above the centre.
+// Second word of a staged record.  The record's FP32 centre relative to the
+// tile is rounded; records whose Gaussian reaches the tile also carry that
+// rounding error cl (x - rho is then formed as (u - centre) + (ul - cl), see
+// PhasePts).  Symmetric peaks: a record without the Gaussian holds its
+// window [lo, hi) as grid indices; a record with it holds the window
+// relative to the tile (both ends clamped to [0, kTile], packed as
+// lo | hi << 16) and cl.  Asymmetric peaks: the window, the scale above the
+// centre and cl.
 template <bool ASYM>
 struct WinRec2 {
-    int lo, hi;
+    int w0, w1;
+    template <bool GAUSS>
+    __device__ __forceinline__ static WinRec2 make(int lo, int hi, int i0,
+                                                   float, float cl) {
+        if (!GAUSS) return WinRec2{lo, hi};
+        const int rl = min(max(lo - i0, 0), kTile), rh = min(max(hi - i0, 0), kTile);
+        return WinRec2{rl | (rh << 16), __float_as_int(cl)};
+    }
+    // first point and length of the window, in the indices `rel` says
+    template <bool GAUSS>
+    __device__ __forceinline__ int2 window() const {
+        if (!GAUSS) return make_int2(w0, w1 - w0);
+        const int rl = w0 & 0xffff;
+        return make_int2(rl, (w0 >> 16) - rl);
+    }
+    template <bool GAUSS>
+    __device__ __forceinline__ static constexpr bool rel() { return GAUSS; }
     __device__ __forceinline__ float ahi(float alo) const { return alo; }
+    __device__ __forceinline__ float cl() const { return __int_as_float(w1); }
 };
 template <>
 struct WinRec2<true> {
     int lo, hi;
-    float ah, pad;
+    float ah, cl_;
+    template <bool GAUSS>
+    __device__ __forceinline__ static WinRec2 make(int lo, int hi, int,
+                                                   float ah, float cl) {
+        return WinRec2{lo, hi, ah, cl};
+    }
+    template <bool GAUSS>
+    __device__ __forceinline__ int2 window() const {
+        return make_int2(lo, hi - lo);
+    }
+    template <bool GAUSS>
+    __device__ __forceinline__ static constexpr bool rel() { return false; }
     __device__ __forceinline__ float ahi(float) const { return ah; }
+    __device__ __forceinline__ float cl() const { return cl_; }
 };
 
 template <bool ASYM, int CAP = kWinPeaks>
 struct WinSmem {
     static constexpr int kCap = CAP;
     float4 rec[CAP];                // (centre, 2c/(Aw) below, amp L, amp G)
-    WinRec2<ASYM> rec2[CAP];        // (lo, hi[, 2c/(alpha w)])
+    WinRec2<ASYM> rec2[CAP];        // window[, 2c/(alpha w)], centre's error
     int wmax[kWaves], wmaxn[kWaves], wcnt[kWaves], wcntg[kWaves];
     float sig[kWaves][kTile];
     float rres[kTile];
@@ -1043,33 +1119,33 @@ struct WinSmem {
 template <bool ASYM, bool SEC>
 __device__ void win_phase_global(const SegPeaks &sp, int4 r, int2 r2,
                                  float4 cst, float iw2r,
-                                 const float (&u)[kPPL], const int (&idx)[kPPL],
-                                 float (&sig)[kPPL]) {
+                                 const float (&u)[kPPL], const float (&ul)[kPPL],
+                                 const int (&idx)[kPPL], float (&sig)[kPPL]) {
     const int ja = __builtin_amdgcn_readfirstlane(r.x);
     const int ga = __builtin_amdgcn_readfirstlane(r.y);
     const int gb = __builtin_amdgcn_readfirstlane(r.z);
     const int jb = __builtin_amdgcn_readfirstlane(r.w);
     const float iw2 = cst.x, aG = cst.y, aL = cst.z, mu = cst.w;
-    float uq[kPPL], uqr[kPPL], accL[kPPL], accG[kPPL];
+    PhasePts pp;
+    pp.set(u, ul, mu, iw2, iw2r, ASYM);
+    float accL[kPPL], accG[kPPL];
 #pragma unroll
     for (int p = 0; p < kPPL; ++p) {
-        uq[p] = (u[p] - mu) * iw2;
-        uqr[p] = ASYM ? (u[p] - mu) * iw2r : uq[p];
         accL[p] = 0.f;
         accG[p] = 0.f;
     }
     if (ASYM) {
         const int jr = __builtin_amdgcn_readfirstlane(r2.x);
         const int jl = __builtin_amdgcn_readfirstlane(r2.y);
-        fwd_segment<true, false, kAbove, SEC>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
-        fwd_segment<true, true, kAbove, SEC>(sp, ga, jr, idx, uq, uqr, iw2, iw2r, accL, accG);
-        fwd_segment<true, true, kBoth, SEC>(sp, jr, jl, idx, uq, uqr, iw2, iw2r, accL, accG);
-        fwd_segment<true, true, kBelow, SEC>(sp, jl, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
-        fwd_segment<true, false, kBelow, SEC>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
+        fwd_segment<true, false, kAbove, SEC>(sp, ja, ga, idx, u, pp, iw2, iw2r, accL, accG);
+        fwd_segment<true, true, kAbove, SEC>(sp, ga, jr, idx, u, pp, iw2, iw2r, accL, accG);
+        fwd_segment<true, true, kBoth, SEC>(sp, jr, jl, idx, u, pp, iw2, iw2r, accL, accG);
+        fwd_segment<true, true, kBelow, SEC>(sp, jl, gb, idx, u, pp, iw2, iw2r, accL, accG);
+        fwd_segment<true, false, kBelow, SEC>(sp, gb, jb, idx, u, pp, iw2, iw2r, accL, accG);
     } else {
-        fwd_segment<true, false, kBelow, SEC>(sp, ja, ga, idx, uq, uqr, iw2, iw2r, accL, accG);
-        fwd_segment<true, true, kBelow, SEC>(sp, ga, gb, idx, uq, uqr, iw2, iw2r, accL, accG);
-        fwd_segment<true, false, kBelow, SEC>(sp, gb, jb, idx, uq, uqr, iw2, iw2r, accL, accG);
+        fwd_segment<true, false, kBelow, SEC>(sp, ja, ga, idx, u, pp, iw2, iw2r, accL, accG);
+        fwd_segment<true, true, kBelow, SEC>(sp, ga, gb, idx, u, pp, iw2, iw2r, accL, accG);
+        fwd_segment<true, false, kBelow, SEC>(sp, gb, jb, idx, u, pp, iw2, iw2r, accL, accG);
     }
 #pragma unroll
     for (int p = 0; p < kPPL; ++p)
@@ -1077,20 +1153,25 @@ __device__ void win_phase_global(const SegPeaks &sp, int4 r, int2 r2,
 }
 
 // One staged record's terms at the lane's points (a: centre, scale below,
-// Lorentzian and Gaussian amplitudes; b: window and the scale above).
+// Lorentzian and Gaussian amplitudes; b: window, the scale above and, with
+// the Gaussian, the centre's rounding error).
 template <bool ASYM, bool GAUSS>
 __device__ __forceinline__ void win_record(const float4 a, const WinRec2<ASYM> b,
                                            const float (&u)[kPPL],
-                                           const int (&idx)[kPPL],
+                                           const float (&ul)[kPPL],
+                                           const int (&idx)[kPPL], int i0,
                                            float (&sig)[kPPL]) {
     const float ah = b.ahi(a.y);
-    const unsigned span = (unsigned)(b.hi - b.lo);
+    const int2 wnd = b.template window<GAUSS>();
+    const float cl = GAUSS ? b.cl() : 0.f;
 #pragma unroll
     for (int p = 0; p < kPPL; ++p) {
         // only the lanes whose point lies in the window take part: a half
         // tile the window misses is skipped by the whole wave
-        if ((unsigned)(idx[p] - b.lo) < span) {
-            const float d = u[p] - a.x;
+        const int ii = WinRec2<ASYM>::template rel<GAUSS>() ? idx[p] - i0 : idx[p];
+        if ((unsigned)(ii - wnd.x) < (unsigned)wnd.y) {
+            float d = u[p] - a.x;
+            if (GAUSS) d += ul[p] - cl;
             const float q2 = d * (ASYM ? (d >= 0.f ? ah : a.y) : a.y);
             const float tt = fmaf(q2, q2, 1.0f);
             sig[p] = fmaf(a.z, rcp_f32(tt), sig[p]);
@@ -1136,18 +1217,20 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
     const double xa = P.x[i0], xb = P.x[i1 - 1];
     SegPeaks sp;
     sp.pt = as_const(ptt);
+    sp.ptl = as_const(P.ptl + (size_t)t * P.T);
     sp.inten = as_const(P.inten);
     sp.wlo = as_const(wlo);
     sp.whi = as_const(whi);
     sp.sec = as_const(psec);
 
-    float u[kPPL];
+    float u[kPPL], ul[kPPL];
     int idx[kPPL];
     float sig[kPPL];
 #pragma unroll
     for (int p = 0; p < kPPL; ++p) {
         idx[p] = i0 + p * kWave + lane;
         u[p] = P.u[idx[p]];
+        ul[p] = P.ul[idx[p]];
         sig[p] = 0.f;
     }
 
@@ -1185,9 +1268,10 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
         // the front, the others from the back, each in phase and peak order.
         const bool fits = tid < nk && incl <= kCap;
         if (fits) {
-            const float iw2 = cst.x, aG = cst.y, aL = cst.z, mu = cst.w;
-            // The tile-relative centre comes from the FP64 position (as the
-            // per-tile table is formed), the window from the window step's
+            const float iw2 = cst.x, aG = cst.y, aL = cst.z;
+            // The tile-relative centre comes from the FP64 position and
+            // shift (rounded once, its rounding error kept for the records
+            // with the Gaussian), the window from the window step's
             // own bounds and grid search (constant width), and the side of
             // an asymmetric peak from the predicates of the tile plan's side
             // searches.
@@ -1216,14 +1300,15 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
                 const int slot = gauss ? exclg + (j - gr.x)
                                        : kCap - 1 - excln -
                                              (j < gr.x ? j - pw.ja : q - cg);
-                sm.rec[slot] = make_float4((float)(pj - xref) + mu, alo, I * aL,
-                                           gauss ? I * aG : 0.f);
+                const double cx = (pj - xref) + pw.mu;
+                const float cxf = (float)cx;
+                sm.rec[slot] = make_float4(cxf, alo, I * aL, gauss ? I * aG : 0.f);
                 const int2 wnd = SEC ? make_int2(wlo[j], whi[j]) : grid_finish(P.x, P.N, gp);
-                WinRec2<ASYM> w2;
-                w2.lo = wnd.x;
-                w2.hi = wnd.y < wnd.x ? wnd.x : wnd.y;
-                if constexpr (ASYM) { w2.ah = ahi; w2.pad = 0.f; }
-                sm.rec2[slot] = w2;
+                const int whi_j = wnd.y < wnd.x ? wnd.x : wnd.y;
+                const float cl = (float)(cx - (double)cxf);
+                sm.rec2[slot] = gauss
+                    ? WinRec2<ASYM>::template make<true>(wnd.x, whi_j, i0, ahi, cl)
+                    : WinRec2<ASYM>::template make<false>(wnd.x, whi_j, i0, ahi, cl);
             }
         }
         // staged record counts and number of fitting phases
@@ -1249,18 +1334,18 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
         // the waves share the two lists
 #pragma unroll 2
         for (int f = wv; f < n_g; f += kWaves)
-            win_record<ASYM, true>(sm.rec[f], sm.rec2[f], u, idx, sig);
+            win_record<ASYM, true>(sm.rec[f], sm.rec2[f], u, ul, idx, i0, sig);
 #pragma unroll 2
         for (int f = wv; f < n_n; f += kWaves)
             win_record<ASYM, false>(sm.rec[kCap - 1 - f],
-                                    sm.rec2[kCap - 1 - f], u, idx, sig);
+                                    sm.rec2[kCap - 1 - f], u, ul, idx, i0, sig);
         // phases that did not fit (every lane finds the same ranges)
         for (int kl = n_fit + wv; kl < nk; kl += kWaves) {
             const int k = c0 + kl;
             int2 rk2 = make_int2(0, 0);
             const int4 rk = tile_range<SEC>(P, st, st.phi, s, t, k, ASYM ? &rk2 : nullptr);
             win_phase_global<ASYM, SEC>(sp, rk, rk2, pkv[k], ASYM ? pkrv[k] : 0.f,
-                                        u, idx, sig);
+                                        u, ul, idx, sig);
         }
         __syncthreads();                       // records consumed
     }

@@ -12,8 +12,10 @@
 
 namespace xrdvi {
 
-hipError_t launch_prepare(const ProbDev &P, double *lgy, float *u, float *pt,
-                          hipStream_t stream);
+// Per-problem tables: ln y!, the tile-relative FP32 grid and peak positions
+// and the rounding errors of both.
+hipError_t launch_prepare(const ProbDev &P, double *lgy, float *u, float *ul,
+                          float *pt, float *ptl, hipStream_t stream);
 hipError_t launch_sample(const ProbDev &P, const StepDev &st,
                          const double *loc, const double *logscale,
                          const double *eps, uint64_t seed, uint64_t step,

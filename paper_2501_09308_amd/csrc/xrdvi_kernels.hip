@@ -7,25 +7,33 @@
 namespace xrdvi {
 
 // Problem preparation: ln y!, tile-relative FP32 grid and peak positions.
-__global__ void k_prepare_points(ProbDev P, double *lgy, float *u) {
+__global__ void k_prepare_points(ProbDev P, double *lgy, float *u, float *ul) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.ntiles * kTile) return;
     const int t = i / kTile;
     const double xref = P.x[min(t * kTile + kTile / 2, P.N - 1)];
     if (i < P.N) {
         lgy[i] = lgamma(P.y[i] + 1.0);
-        u[i] = (float)(P.x[i] - xref);
+        const double v = P.x[i] - xref;
+        const float vh = (float)v;
+        u[i] = vh;
+        ul[i] = (float)(v - (double)vh);
     } else {
         u[i] = 0.f;
+        ul[i] = 0.f;
     }
 }
 
-__global__ void k_prepare_peaks(ProbDev P, float *pt) {
+__global__ void k_prepare_peaks(ProbDev P, float *pt, float *ptl) {
     const int t = blockIdx.y;
     const double xref = P.x[min(t * kTile + kTile / 2, P.N - 1)];
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < P.T;
-         j += gridDim.x * blockDim.x)
-        pt[(size_t)t * P.T + j] = (float)(P.pos[j] - xref);
+         j += gridDim.x * blockDim.x) {
+        const double v = P.pos[j] - xref;
+        const float vh = (float)v;
+        pt[(size_t)t * P.T + j] = vh;
+        ptl[(size_t)t * P.T + j] = (float)(v - (double)vh);
+    }
 }
 
 // a1: grid (ceil(K/64), S), 256 threads.
@@ -157,13 +165,13 @@ __global__ void k_adam(int n, double *theta, double *m1, double *m2,
 
 // ---- launchers ------------------------------------------------------------
 
-hipError_t launch_prepare(const ProbDev &P, double *lgy, float *u, float *pt,
-                          hipStream_t stream) {
+hipError_t launch_prepare(const ProbDev &P, double *lgy, float *u, float *ul,
+                          float *pt, float *ptl, hipStream_t stream) {
     const int np = P.ntiles * kTile;
-    k_prepare_points<<<(np + 255) / 256, 256, 0, stream>>>(P, lgy, u);
+    k_prepare_points<<<(np + 255) / 256, 256, 0, stream>>>(P, lgy, u, ul);
     if (P.T > 0) {
         dim3 g((P.T + 255) / 256 < 64 ? (P.T + 255) / 256 : 64, P.ntiles);
-        k_prepare_peaks<<<g, 256, 0, stream>>>(P, pt);
+        k_prepare_peaks<<<g, 256, 0, stream>>>(P, pt, ptl);
     }
     return hipGetLastError();
 }

@@ -118,7 +118,13 @@ def test_window_wider_than_the_grid_equals_dense():
                          dev(phi)).cpu().numpy()
     fw = X.xrdvi_profile(ctx, X.Problem.from_workload(ctx, prob, y, cutoff=1e6),
                          dev(phi)).cpu().numpy()
-    # the windowed forward forms x - rho as u - (p + mu) in FP32, the dense
-    # one through a fused multiply-add: each is within the profile bar of the
-    # oracle, and of each other
-    np.testing.assert_allclose(fw, f0, rtol=2e-5)
+    # a window wider than the grid keeps every peak: both are the dense
+    # oracle profile within the profile bar, and each other within the FP32
+    # rounding of their different summation orders
+    ref = oracle.profile(prob.x, prob.bg, prob.peak_off, prob.peak_pos,
+                         prob.peak_int, 0.0, phi)
+    e0 = np.max(np.abs(f0 - ref) / ref)
+    ew = np.max(np.abs(fw - ref) / ref)
+    print(f"\nwide window: dense {e0:.2e}, windowed {ew:.2e} vs the dense oracle")
+    assert e0 <= 1e-5 and ew <= 1e-5
+    np.testing.assert_allclose(fw, f0, rtol=2e-6)

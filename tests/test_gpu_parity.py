@@ -1,9 +1,10 @@
 """GPU parity of the HIP path against the FP64 oracle, through the C ABI.
 
 Tolerances: ELBO relative <= 1e-6 and gradient relative L2 <= 1e-4 (the
-stated bar); the FP32 profile is held to a relative bound derived from the
-tile-relative FP32 arithmetic (see the design notes); integer window plans
-are compared bit for bit.
+stated bar); the FP32 profile is held to max relative 1e-5 (each peak term
+carries a few units of FP32 rounding in x - rho and in its evaluation, and
+the per-phase sums add a few more: measured errors stay below 1e-6);
+integer window plans are compared bit for bit.
 """
 import numpy as np
 import pytest
@@ -17,7 +18,7 @@ from gpu_common import case, context, dev, rel_l2
 
 pytestmark = pytest.mark.gpu
 
-PROFILE_RTOL = 2e-5     # max |f_gpu - f| / f over all points and samples
+PROFILE_RTOL = 1e-5     # max |f_gpu - f| / f over all points and samples
 ELBO_RTOL = 1e-6
 GRAD_RTOL = 1e-4
 

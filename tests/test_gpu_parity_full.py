@@ -1,5 +1,6 @@
-"""GPU parity at the full sizes of the larger workloads, on outputs the
-oracle can compute one by one or via properties that hold at any size.
+"""GPU parity at the full sizes of the larger workloads: the ELBO, every
+per-sample log-likelihood and the gradient at the stated sample counts,
+plus window-plan properties and sampled profile points.
 
 stress200: N=7001 (10-80 deg at 0.01), K=200 x 60 peaks, S=128, dense.
 db2000:    N=14001 (10-150 deg at 0.01), K=2000 x 100 peaks, S=32, c=8.
@@ -47,7 +48,23 @@ def db():
     return prob, y
 
 
-def test_stress200_full_elbo_and_sampled_logliks(stress):
+def _compare(tag, e, ll, g, re, rll, rg):
+    erel = abs(e - re) / abs(re)
+    lrel = np.max(np.abs(ll - rll) / np.abs(rll))
+    grel = rel_l2(g, rg)
+    print(f"\n{tag}: elbo rel {erel:.2e}, max loglik rel {lrel:.2e}, "
+          f"grad rel-L2 {grel:.2e}")
+    assert erel <= 1e-6 and lrel <= 1e-6
+    assert grel <= 1e-4
+
+
+def test_stress200_full_size_S128_through_autograd(stress):
+    """The stated differentiation-stress configuration as a whole: N=7001,
+    K=200 x 60, S=128 (two 64-sample groups in the gradient and ELBO
+    reductions), forward and recomputing adjoint through the autograd
+    Function; every per-sample log-likelihood, the ELBO and the full
+    gradient against the oracle (Sec. 3.2: the estimate and its gradient
+    are averages of per-sample terms)."""
     prob, y = stress
     ctx = context()
     P = X.Problem.from_workload(ctx, prob, y)
@@ -55,34 +72,35 @@ def test_stress200_full_elbo_and_sampled_logliks(stress):
     loc, logscale = W.random_params(prob.K, 3003, (y - prob.bg).max())
     eps = W.eps_draw(S, prob.K, 3004)
     tape = X.Tape(ctx, P, S)
-    e, ll = X.xrdvi_elbo_fwd(ctx, P, tape, dev(loc), dev(logscale), eps=dev(eps))
-    ll = ll.cpu().numpy()
-    pick = [0, 41, 127]
-    _, rll, _, _ = oracle.elbo(prob, y, loc, logscale, eps[pick], grad=False)
-    err = np.max(np.abs(ll[pick] - rll) / np.abs(rll))
-    print(f"\nstress200 S=128 sampled loglik max rel {err:.2e}")
-    assert err <= 1e-6
-    assert np.isfinite(e.item())
-
-
-def test_stress200_full_size_gradient(stress):
-    prob, y = stress
-    ctx = context()
-    P = X.Problem.from_workload(ctx, prob, y)
-    S = 6
-    loc, logscale = W.random_params(prob.K, 3005, (y - prob.bg).max())
-    eps = W.eps_draw(S, prob.K, 3006)
     L = dev(loc).requires_grad_(True)
     Ls = dev(logscale).requires_grad_(True)
-    out = X.elbo(ctx, P, X.Tape(ctx, P, S), L, Ls, eps=dev(eps))
+    out = X.elbo(ctx, P, tape, L, Ls, eps=dev(eps))
     out.backward()
-    re, _, rgl, rgs = oracle.elbo(prob, y, loc, logscale, eps)
+    # the tape keeps the per-sample log-likelihoods of that forward
+    _, ll = X.xrdvi_elbo_fwd(ctx, P, tape, dev(loc), dev(logscale), eps=dev(eps),
+                             need_grad=False)
+    re, rll, rgl, rgs = oracle.elbo(prob, y, loc, logscale, eps)
     g = np.concatenate([L.grad.cpu().numpy().ravel(), Ls.grad.cpu().numpy().ravel()])
-    rg = np.concatenate([rgl.ravel(), rgs.ravel()])
-    print(f"\nstress200 S={S}: elbo rel {abs(out.item() - re) / abs(re):.2e} "
-          f"grad rel-L2 {rel_l2(g, rg):.2e}")
-    assert abs(out.item() - re) / abs(re) <= 1e-6
-    assert rel_l2(g, rg) <= 1e-4
+    _compare("stress200 S=128", out.item(), ll.cpu().numpy(), g, re, rll,
+             np.concatenate([rgl.ravel(), rgs.ravel()]))
+
+
+def test_stress200_sample_count_not_a_multiple_of_64():
+    """S = 100 (a full and a partial 64-sample group) on a shorter grid."""
+    prob = W.make_problem("stress200", 3011, N=1500)
+    y = counts(prob, 3012)
+    ctx = context()
+    P = X.Problem.from_workload(ctx, prob, y)
+    S = 100
+    loc, logscale = W.random_params(prob.K, 3013, (y - prob.bg).max())
+    eps = W.eps_draw(S, prob.K, 3014)
+    tape = X.Tape(ctx, P, S)
+    e, ll = X.xrdvi_elbo_fwd(ctx, P, tape, dev(loc), dev(logscale), eps=dev(eps))
+    gl, gs = X.xrdvi_elbo_bwd(ctx, tape)
+    re, rll, rgl, rgs = oracle.elbo(prob, y, loc, logscale, eps)
+    g = np.concatenate([gl.cpu().numpy().ravel(), gs.cpu().numpy().ravel()])
+    _compare("stress200 N=1500 S=100", e.item(), ll.cpu().numpy(), g, re, rll,
+             np.concatenate([rgl.ravel(), rgs.ravel()]))
 
 
 def test_db2000_window_plan_properties(db):
@@ -124,31 +142,15 @@ def test_db2000_profile_on_sampled_points(db):
                          prob.cutoff, phi)
     err = np.max(np.abs(f[:, idx] - ref) / ref)
     print(f"\ndb2000 sampled profile max rel {err:.2e}")
-    assert err <= 2e-5
+    assert err <= 1e-5
 
 
-def test_db2000_full_elbo_and_gradient_small_S(db):
-    prob, y = db
-    ctx = context()
-    P = X.Problem.from_workload(ctx, prob, y)
-    S = 2
-    loc, logscale = W.random_params(prob.K, 5005, (y - prob.bg).max())
-    eps = W.eps_draw(S, prob.K, 5006)
-    tape = X.Tape(ctx, P, S)
-    e, ll = X.xrdvi_elbo_fwd(ctx, P, tape, dev(loc), dev(logscale), eps=dev(eps))
-    gl, gs = X.xrdvi_elbo_bwd(ctx, tape)
-    re, rll, rgl, rgs = oracle.elbo(prob, y, loc, logscale, eps)
-    g = np.concatenate([gl.cpu().numpy().ravel(), gs.cpu().numpy().ravel()])
-    rg = np.concatenate([rgl.ravel(), rgs.ravel()])
-    print(f"\ndb2000 S={S}: elbo rel {abs(e.item() - re) / abs(re):.2e} "
-          f"grad rel-L2 {rel_l2(g, rg):.2e}")
-    assert abs(e.item() - re) / abs(re) <= 1e-6
-    assert rel_l2(g, rg) <= 1e-4
-
-
-def test_db2000_full_sample_count_runs(db):
-    """S = 32 at full size with device noise: bitwise repeatable, finite,
-    and two samples' log-likelihoods match the oracle."""
+def test_db2000_full_size_S32_device_noise(db):
+    """The stated database-screening configuration as a whole: N=14001,
+    K=2000 x 100, S=32, c=8, with the device's Philox noise (the oracle
+    draws the same numbers from its own generator).  Two runs are bitwise
+    equal; all 32 per-sample log-likelihoods, the ELBO and the gradient
+    match the oracle."""
     prob, y = db
     ctx = context()
     P = X.Problem.from_workload(ctx, prob, y)
@@ -163,9 +165,9 @@ def test_db2000_full_sample_count_runs(db):
         outs.append([t.cpu().numpy().copy() for t in (e, ll, gl, gs)])
     for a, b in zip(*outs):
         assert np.array_equal(a, b) and np.all(np.isfinite(a))
-    # the per-sample likelihoods of two samples match the oracle
     eps = oracle.eps_philox(S, prob.K, 11, 3)
-    _, rll, _, _ = oracle.elbo(prob, y, loc, logscale, eps[:2], grad=False)
-    err = np.max(np.abs(outs[0][1][:2] - rll) / np.abs(rll))
-    print(f"\ndb2000 S=32 device noise: sampled loglik max rel {err:.2e}")
-    assert err <= 1e-6
+    re, rll, rgl, rgs = oracle.elbo(prob, y, loc, logscale, eps)
+    e, ll, gl, gs = outs[0]
+    g = np.concatenate([gl.ravel(), gs.ravel()])
+    _compare("db2000 S=32", float(e[0]), ll, g, re, rll,
+             np.concatenate([rgl.ravel(), rgs.ravel()]))
