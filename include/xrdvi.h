@@ -169,6 +169,22 @@ XRDVI_API int xrdvi_profile(xrdvi_ctx *ctx, const xrdvi_problem *prob,
                             void *stream);
 
 /*
+ * Allocation-free variant of xrdvi_profile, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, kernels and results (bit for bit)
+ * as xrdvi_profile; the per-call state lives in a static 64 MiB device array
+ * of the library (one per GPU, held until the process ends; its address is
+ * looked up once per device by xrdvi_ctx_create), and the call allocates
+ * nothing.  A problem and S whose per-call state needs more than 64 MiB are
+ * rejected with XRDVI_EINVAL (xrdvi_profile serves them).  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (different
+ * streams, or threads) race and give unspecified output; serialise them.
+ */
+XRDVI_API int xrdvi_profile_static(xrdvi_ctx *ctx, const xrdvi_problem *prob,
+                                   int32_t S, const double *phi, float *f_out,
+                                   void *stream);
+
+/*
  * Window plan: for each sample s and peak m (caller's peak order),
  * lo[s][m] = first grid index inside [rho - c w, rho + c w] (upper bound
  * rho + (c w) alpha for asymmetric peaks) and hi[s][m] = one past the last

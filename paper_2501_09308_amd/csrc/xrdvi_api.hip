@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -219,6 +220,49 @@ hipError_t upload_problem(const xrdvi_problem_desc &d, double lambda,
 
 }  // namespace xrdvi
 
+// ---- scratch of the allocation-free profile entry ------------------------
+//
+// xrdvi_profile_static keeps its per-call state (phase constants, window
+// plan, tile ranges, per-tile likelihoods) in this file-scope device array
+// instead of the context workspace.  Each GPU the library runs on holds its
+// own copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, never the device memory: host code uses the per-device address
+// that hipGetSymbolAddress returns (looked up once per device, with that
+// device current, by xrdvi_ctx_create).
+namespace xrdvi {
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;   // 64 MiB
+constexpr int kMaxDevices = 64;
+}  // namespace xrdvi
+
+static __device__ __align__(256) unsigned char scratch[xrdvi::kStaticScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[xrdvi::kMaxDevices] = {};
+
+// Device address of this device's scratch (the current device must be
+// `dev`); looked up on the first call per device.
+hipError_t static_scratch_lookup(int dev, void **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+void *static_scratch(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
 namespace {
 
 struct DeviceGuard {
@@ -400,6 +444,13 @@ int xrdvi_ctx_create(int device, xrdvi_ctx **out) {
     HIP_TRY(hipGetDeviceCount(&n), "hipGetDeviceCount");
     if (device < 0 || device >= n)
         return fail(XRDVI_EINVAL, "device index out of range");
+    if (device >= kMaxDevices)
+        return fail(XRDVI_EINVAL, "device index beyond the library's 64-device table");
+    {
+        DeviceGuard g(device);
+        void *ptr = nullptr;
+        HIP_TRY(static_scratch_lookup(device, &ptr), "static scratch address");
+    }
     auto *c = new xrdvi_ctx();
     c->device = device;
     *out = c;
@@ -533,6 +584,37 @@ int xrdvi_profile(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
     HIP_TRY(launch_peak_plan(P, st, phi, s), "window plan");
     HIP_TRY(launch_plan(P, st, phi, s), "tile plan");
     HIP_TRY(timed_fused(ctx, P, st, false, f_out, s), "profile");
+    return XRDVI_OK;
+    API_GUARD_END
+}
+
+int xrdvi_profile_static(xrdvi_ctx *ctx, const xrdvi_problem *prob, int32_t S,
+                         const double *phi, float *f_out, void *stream) {
+    API_GUARD_BEGIN
+    if (!ctx || !prob || !phi || !f_out) return fail(XRDVI_EINVAL, "NULL argument");
+    if (prob->ctx != ctx) return fail(XRDVI_EINVAL, "problem belongs to another context");
+    if (S < 1 || S > kMaxSamples) return fail(XRDVI_EINVAL, "S must be in [1, 1024]");
+    const ProbDev &P = prob->P;
+    const StepShape sh = step_shape(P, S);
+    const size_t bytes = step_bytes(sh);
+    if (bytes > kStaticScratchBytes)
+        return fail(XRDVI_EINVAL,
+                    "xrdvi_profile_static: this problem and S need " +
+                        std::to_string(bytes) + " bytes of scratch, more than the " +
+                        std::to_string(kStaticScratchBytes) +
+                        " of the static scratch (use xrdvi_profile or a smaller S)");
+    void *base = static_scratch(ctx->device);
+    if (!base) return fail(XRDVI_EDEVICE, "static scratch address not set up for this device");
+    DeviceGuard g(ctx->device);
+    StepDev st = carve_step(base, sh);
+    st.phi = const_cast<double *>(phi);   // read only: the kernels' samples
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // every scratch value these kernels read is written earlier in the same
+    // sequence, so nothing needs clearing between calls
+    HIP_TRY(launch_phi_consts(P, S, phi, st.pk, st.pkr, s), "phi constants");
+    HIP_TRY(launch_peak_plan(P, st, phi, s), "window plan");
+    HIP_TRY(launch_plan(P, st, phi, s), "tile plan");
+    HIP_TRY(launch_fused(P, st, false, f_out, s), "profile");
     return XRDVI_OK;
     API_GUARD_END
 }

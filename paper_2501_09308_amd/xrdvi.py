@@ -113,6 +113,7 @@ def load():
         "xrdvi_tape_create": ([_VP, _VP, i32, C.POINTER(_VP)], C.c_int),
         "xrdvi_tape_destroy": ([_VP], C.c_int),
         "xrdvi_profile": ([_VP, _VP, i32, _VP, _VP, _VP], C.c_int),
+        "xrdvi_profile_static": ([_VP, _VP, i32, _VP, _VP, _VP], C.c_int),
         "xrdvi_window_plan": ([_VP, _VP, i32, _VP, _VP, _VP, _VP], C.c_int),
         "xrdvi_elbo_fwd": ([_VP, _VP, i32, _VP, _VP, _VP, u64, u64, i32, _VP,
                             _VP, _VP, _VP], C.c_int),
@@ -315,6 +316,23 @@ def xrdvi_profile(ctx: Context, prob: Problem, phi: torch.Tensor,
         out = torch.empty((S, prob.N), dtype=torch.float32, device=phi.device)
     _check(ctx.lib.xrdvi_profile(ctx.handle, prob.handle, S, _ptr(phi), _ptr(out),
                                  _stream(phi.device)))
+    return out
+
+
+def xrdvi_profile_static(ctx: Context, prob: Problem, phi: torch.Tensor,
+                         out: torch.Tensor) -> torch.Tensor:
+    """As xrdvi_profile, through the allocation-free entry point: the caller
+    passes the output f[S][N] (float32, device)."""
+    if phi.dim() == 2:
+        phi = phi.unsqueeze(0)
+    S = phi.shape[0]
+    phi = _dev_f64(phi, (S, prob.D, prob.K), "phi")
+    if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+            and tuple(out.shape) == (S, prob.N)):
+        raise TypeError(f"out must be a contiguous float32 CUDA tensor of shape "
+                        f"({S}, {prob.N})")
+    _check(ctx.lib.xrdvi_profile_static(ctx.handle, prob.handle, S, _ptr(phi),
+                                        _ptr(out), _stream(phi.device)))
     return out
 
 
