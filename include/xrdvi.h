@@ -185,7 +185,11 @@ XRDVI_API int xrdvi_profile_static(xrdvi_ctx *ctx, const xrdvi_problem *prob,
                                    void *stream);
 
 /*
- * Window plan: for each sample s and peak m (caller's peak order),
+ * Window plan: the points whose peak sum (Appendix A.2, profile function)
+ * includes peak m at sample s.  The paper sums every peak over every point
+ * (Sec. 2.3, the dense peak function); here a peak's terms are kept within
+ * c full widths of its centre, and c = 0 is the paper's dense sum.  For
+ * each sample s and peak m (caller's peak order),
  * lo[s][m] = first grid index inside [rho - c w, rho + c w] (upper bound
  * rho + (c w) alpha for asymmetric peaks) and hi[s][m] = one past the last
  * (lo = hi when empty), with rho = p_m + mu and the bounds formed in FP64 by
@@ -223,7 +227,10 @@ XRDVI_API int xrdvi_elbo_fwd(xrdvi_ctx *ctx, const xrdvi_problem *prob,
                              xrdvi_tape *tape, void *stream);
 
 /*
- * ELBO gradient: g times dL/dloc and dL/dlogscale of the estimate computed
+ * ELBO gradient.  The method turns inference into an optimisation solved by
+ * the gradient method with stochastic VI (Sec. 2.1), maximising the ELBO
+ * over the mean-field Gaussian's parameters (Sec. 3.2); this call gives
+ * g times dL/dloc and dL/dlogscale of the reparameterised estimate computed
  * by the last xrdvi_elbo_fwd on this tape (which must have had need_grad
  * set; else XRDVI_EINVAL), with g = grad_scale, further multiplied by
  * *grad_scale_dev when that device pointer is non-NULL (an upstream
@@ -312,6 +319,12 @@ XRDVI_API int xrdvi_server_destroy(xrdvi_server *srv);
  * full.  Thread-safe. */
 XRDVI_API int xrdvi_submit(xrdvi_server *srv, const xrdvi_request *req,
                            uint64_t *ticket);
+/* Arena bytes a request occupies while resident (its problem, per-step
+ * state, variational and Adam state and ELBO trace, in 256-byte aligned
+ * pieces), for sizing a server's arena or resident cap.  Host only:
+ * validates the request like xrdvi_submit (XRDVI_EINVAL) and copies
+ * nothing. */
+XRDVI_API int xrdvi_request_footprint(const xrdvi_request *req, size_t *bytes);
 /* XRDVI_PENDING while queued or running; XRDVI_OK once the outputs have
  * been written (reported once: the ticket is then forgotten and later
  * polls return XRDVI_ENOENT); XRDVI_ECANCELED, XRDVI_ENONFINITE or

@@ -403,6 +403,17 @@ int xrdvi_submit(xrdvi_server *srv, const xrdvi_request *req, uint64_t *ticket) 
     API_GUARD_END
 }
 
+int xrdvi_request_footprint(const xrdvi_request *req, size_t *bytes) {
+    API_GUARD_BEGIN
+    if (!bytes) return fail(XRDVI_EINVAL, "NULL argument");
+    std::unique_ptr<Job> j;
+    const int rc = make_job(req, &j);
+    if (rc != XRDVI_OK) return rc;
+    *bytes = slot_layout(*j).total;
+    return XRDVI_OK;
+    API_GUARD_END
+}
+
 int xrdvi_poll(xrdvi_server *srv, uint64_t ticket, xrdvi_status *st) {
     API_GUARD_BEGIN
     if (!srv) return fail(XRDVI_EINVAL, "NULL argument");

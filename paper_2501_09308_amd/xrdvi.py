@@ -125,6 +125,8 @@ def load():
         "xrdvi_server_destroy": ([_VP], C.c_int),
         "xrdvi_submit": ([_VP, C.POINTER(Request), C.POINTER(C.c_uint64)], C.c_int),
         "xrdvi_poll": ([_VP, C.c_uint64, C.POINTER(Status)], C.c_int),
+        "xrdvi_request_footprint": ([C.POINTER(Request), C.POINTER(C.c_size_t)],
+                                    C.c_int),
         "xrdvi_cancel": ([_VP, C.c_uint64], C.c_int),
         "xrdvi_server_clock": ([_VP], C.c_double),
         "xrdvi_plain_run": ([_VP, C.POINTER(Request), C.POINTER(Status), _VP],
@@ -541,6 +543,14 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def request_footprint(prob, y, S, steps, seed=0, **kw) -> int:
+    """Arena bytes the request would occupy while resident (host only)."""
+    sub = _Submission(*_request_args(prob, y, S, steps, seed, 0.0, None, **kw))
+    out = C.c_size_t()
+    _check(load().xrdvi_request_footprint(C.byref(sub.req), C.byref(out)))
+    return int(out.value)
 
 
 def xrdvi_plain_run(ctx: Context, prob, y, S, steps, seed, lr=0.0, init=None,

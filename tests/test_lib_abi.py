@@ -92,3 +92,17 @@ def test_null_description_is_rejected():
     lib = X.load()
     assert lib.xrdvi_validate(None) == X.XRDVI_EINVAL
     assert b"NULL" in lib.xrdvi_last_error()
+
+
+def test_request_footprint_is_host_only_and_grows_with_the_request():
+    prob = W.make_problem("tiny", seed=3, N=300, K=3, M=4)
+    y = np.full(prob.N, 60.0)
+    small = X.request_footprint(prob, y, S=4, steps=10)
+    assert small > 0 and small % 256 == 0
+    assert X.request_footprint(prob, y, S=32, steps=10) > small
+    assert X.request_footprint(prob, y, S=4, steps=5000) > small
+    big = W.make_problem("tiny", seed=3, N=3000, K=30, M=40)
+    assert X.request_footprint(big, np.full(big.N, 60.0), S=4, steps=10) > small
+    with pytest.raises(X.XrdviError) as ei:
+        X.request_footprint(prob, y, S=0, steps=10)
+    assert ei.value.code == X.XRDVI_EINVAL
