@@ -185,6 +185,13 @@ hipError_t upload_problem(const xrdvi_problem_desc &d, double lambda,
     P.cutoff = d.cutoff;
     P.x0 = d.x[0];
     P.inv_dx = N > 1 ? (double)(N - 1) / (d.x[N - 1] - d.x[0]) : 0.0;
+    P.dx = N > 1 ? (d.x[N - 1] - d.x[0]) / (double)(N - 1) : 0.0;
+    P.uniform = 1;
+    for (int i = 1; i < N; ++i)
+        if (!(std::fabs(d.x[i] - std::fma((double)i, P.dx, d.x[0])) <= 1e-9 * P.dx)) {
+            P.uniform = 0;
+            break;
+        }
     P.lambda = lambda;
     P.mu_sd = d.prior.mu_sd;
     P.w_shape = d.prior.w_shape;

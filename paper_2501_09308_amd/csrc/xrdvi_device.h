@@ -72,6 +72,10 @@ struct ProbDev {
     const double *x, *y, *bg, *lgy;   // [N]; lgy = ln y!
     double x0, inv_dx;                // x[0] and (N - 1) / (x[N-1] - x[0])
                                       // (0 for N = 1): grid-search guesses
+    double dx;                        // (x[N-1] - x[0]) / (N - 1) (0 for N = 1)
+    int uniform;                      // 1: every x_i lies within 1e-9 dx of
+                                      // x0 + i dx (the windowed adjoint then
+                                      // forms x_i instead of loading it)
     const float *u;                   // [ntiles * kTile] x_i - xref_tile
                                       // (FP32, rounded)
     const float *ul;                  // [ntiles * kTile] its rounding
@@ -1375,12 +1379,12 @@ struct AdjPt {
 };
 
 template <bool ASYM, bool SEC>
-__device__ __forceinline__ AdjPt adj_point_L(float R, double d, float iw2,
+__device__ __forceinline__ AdjPt adj_point_L(float R, float d, float iw2,
                                              float iw2r, float c,
                                              const SecW &wl, const SecW &wh,
                                              float (&acc)[ASYM ? 12 : 6]) {
-    const bool up = ASYM && d >= 0.0;
-    const float q2 = (float)d * (up ? iw2r : iw2);
+    const bool up = ASYM && d >= 0.f;
+    const float q2 = d * (up ? iw2r : iw2);
     const float tt = fmaf(q2, q2, 1.0f);
     const float l = rcp_f32(tt);
     const float Rl = R * l;
@@ -1474,6 +1478,8 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
     cptr<float> psec = SEC ? as_const(reinterpret_cast<const float *>(st.psec + (size_t)s * P.T))
                            : nullptr;
     const float ka = ASYM ? (float)ph[4 * K + k] : 1.f;
+    const bool unif = P.uniform != 0;
+    const double xl = fma((double)lane, P.dx, P.x0);   // uniform grid: x0 + lane dx
     const int a = P.off[k], b = P.off[k + 1];
     float acc[NS];
 #pragma unroll
@@ -1511,8 +1517,8 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
             rq[q] = __builtin_amdgcn_make_buffer_rsrc(
                 (void *)(rres_s + lo[q]), (short)0, len[q] * 4, kBufferFlags);
         for (int c = 0; c < span; c += kWave) {
-            float R[kAdjPeaks], rv[kAdjPeaks];
-            double d[kAdjPeaks], xv[kAdjPeaks];
+            float R[kAdjPeaks], rv[kAdjPeaks], d[kAdjPeaks];
+            double xv[kAdjPeaks];
 #pragma unroll
             for (int q = 0; q < kAdjPeaks; ++q) {
                 // every lane loads; points past the grid's end (a window
@@ -1521,16 +1527,19 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
                 const int ii = lo[q] + c + lane;
                 rv[q] = __uint_as_float(
                     __builtin_amdgcn_raw_buffer_load_b32(rq[q], (c + lane) * 4, 0, 0));
-                xv[q] = __builtin_bit_cast(
-                    double, __builtin_amdgcn_raw_buffer_load_b64(x_rs, ii * 8, 0, 0));
+                // a uniform grid's x_i = x0 + i dx is formed in FP64, not
+                // loaded, so only the residuals are read
+                xv[q] = unif ? fma((double)(lo[q] + c), P.dx, xl)
+                             : __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                              x_rs, ii * 8, 0, 0));
             }
-            // all 2 kAdjPeaks loads are issued before the first use, so one
-            // memory latency covers them
+            // all loads are issued before the first use, so one memory
+            // latency covers them
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int q = 0; q < kAdjPeaks; ++q) {
                 R[q] = rv[q] * I[q];
-                d[q] = xv[q] - rho[q];
+                d[q] = (float)(xv[q] - rho[q]);
             }
             AdjPt pt[kAdjPeaks];
             SecW wl[kAdjPeaks], wh[kAdjPeaks];
