@@ -32,8 +32,34 @@ SEED = 2000
 # 26 flops (plus 4 transcendentals, not counted).
 FLOPS_PER_PEAK_POINT = 36
 PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+# Measured chip-wide VALU issue rates (paper_2501_09308_amd/ubench, lane
+# operations per second): full-rate VALU instructions (v_fma_f32) and
+# transcendentals (v_rcp_f32, the slower of rcp and exp); they bound a
+# kernel's time by its executed instruction mix.
+VALU_LANE_OPS_PER_S = 5.04e13
+TRANS_LANE_OPS_PER_S = 1.68e13
 # The dominant kernel of the dense step, as rocprofv3 names it.
 DENSE_KERNEL = "void k_fused<false, true, false, false>"
+
+
+def counter_rates(rec, kernel_ms):
+    """Rates of the dense kernel from its rocprofv3 counters (recorded in
+    profiles/ for the current kernel sources) over the live kernel time:
+    executed FP32 TFLOP/s, the fraction of the instruction-mix issue bound
+    reached, and HBM GB/s; None without a record for these sources."""
+    if not rec or "flops_per_dispatch" not in rec or "valu_per_dispatch" not in rec:
+        return None
+    t = kernel_ms * 1e-3
+    tflops = rec["flops_per_dispatch"] / t / 1e12
+    trans = rec["valu_trans_per_dispatch"]
+    t_issue = 64 * ((rec["valu_per_dispatch"] - trans) / VALU_LANE_OPS_PER_S
+                    + trans / TRANS_LANE_OPS_PER_S)
+    gbs = rec["bytes_per_dispatch"] / t / 1e9
+    return {"executed_tflops": tflops, "executed_frac": tflops / PEAK_FP32_TFLOPS,
+            "issue_bound_frac": t_issue / t, "hbm_gbs": gbs,
+            "hbm_frac": gbs / PEAK_HBM_GBS,
+            "source": "rocprofv3 counters per dispatch (profiles/) over the live kernel time"}
 
 
 def log(msg):
@@ -175,8 +201,9 @@ def run_background(X, W, ctx, prob, lam=1e7, p=0.001, n_iter=15):
 
 def run_hmc(X, W, ctx, prob, chains=8, warm=1000, keep=1000, leapfrog=10):
     """The shape of the paper's SVI-vs-MCMC comparison on this GPU: 1000
-    SVI steps (S=64, one analysis at a time) against Hamiltonian Monte Carlo
-    with 1000 warm-up and 1000 kept iterations on the same problem."""
+    SVI steps (S=64, Adam at step size 0.05, one analysis at a time, with
+    its 1 % area-ratio selection) against Hamiltonian Monte Carlo with 1000
+    warm-up and 1000 kept iterations on the same problem."""
     import torch
     P, y = gpu_problem(X, W, ctx, prob, 0.0)
     ymax = float((y - prob.bg).max())
@@ -190,9 +217,17 @@ def run_hmc(X, W, ctx, prob, chains=8, warm=1000, keep=1000, leapfrog=10):
     torch.cuda.synchronize()
     hmc_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    X.xrdvi_plain_run(ctx, prob, y, 64, 1000, SEED)
+    svi = X.xrdvi_plain_run(ctx, prob, y, 64, 1000, SEED, lr=0.05)
     svi_s = time.perf_counter() - t0
-    return dict(svi_1000_steps_s=svi_s, hmc_s=hmc_s, chains=chains,
+    # the analysis's result: phases whose area ratio exceeds 1 % (Sec. 4)
+    rd = X.xrdvi_readout(prob.peak_off, prob.peak_int, svi["loc"],
+                         svi["logscale"], threshold=0.01)
+    sel = [int(k) for k in rd["selected"]]
+    return dict(svi_1000_steps_s=svi_s,
+                svi_selected=sel, generating=[int(k) for k in prob.true_idx],
+                svi_area_ratio=[float(rd["area_ratio"][k]) for k in sel],
+                svi_sd_over_mean=[float(rd["sd_h"][k] / rd["mean_h"][k]) for k in sel],
+                hmc_s=hmc_s, chains=chains,
                 warmup=warm, draws=keep, leapfrog=leapfrog,
                 gradient_evals=(warm + keep) * leapfrog,
                 mean_accept=float(np.mean(out["accept"])),
@@ -220,17 +255,30 @@ def pct(v, q):
     return float(np.percentile(np.asarray(v), q))
 
 
-def run_serving(X, W, ctx, n, rate, steps, S, seed, max_slots, per_launch,
-                plain_leg=True, resident_mb=0.0):
-    """Continuous batching vs one analysis at a time on the same arrival
-    trace; returns both summaries."""
-    reqs = serving_requests(X, W, ctx, n, seed)
-    arrivals = W.arrival_times(n, rate, seed)
-    # ---- served
+def peak_overlap(intervals):
+    """Largest number of [start, end) intervals open at once."""
+    ev = sorted([(a, 1) for a, _ in intervals] + [(b, -1) for _, b in intervals])
+    cur = best = 0
+    for _, d in ev:
+        cur += d
+        best = max(best, cur)
+    return best
+
+
+def serve(X, reqs, arrivals, S, steps, seed, max_slots, per_launch,
+          arena_bytes, resident_mb=0.0):
+    """Serves the requests on their arrival trace with a server whose arena
+    is a caller-allocated (torch) device buffer; returns a summary and the
+    results in request order.  Times to result run from each request's
+    scheduled arrival, on the server's clock."""
+    import torch
+    n = len(reqs)
+    arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
     srv = X.Server(max_slots=max_slots, steps_per_launch=per_launch,
-                   use_graph=True, arena_bytes=24 << 30,
+                   use_graph=True, arena=arena,
                    resident_bytes=int(resident_mb * (1 << 20)))
     tickets, results = [], {}
+    c0 = srv.clock()
     t0 = time.perf_counter()
     nxt = 0
     while len(results) < n:
@@ -249,41 +297,76 @@ def run_serving(X, W, ctx, n, rate, steps, S, seed, max_slots, per_launch,
                 results[t] = (info, out)
         time.sleep(0.0005)
     srv.close()
+    del arena
     infos = [results[t][0] for t in tickets]
-    ttr = [i["t_done"] - i["t_arrive"] for i in infos]
-    span = max(i["t_done"] for i in infos) - min(i["t_arrive"] for i in infos)
-    served = dict(analyses_per_s=n / span, p50_s=pct(ttr, 50), p99_s=pct(ttr, 99),
-                  makespan_s=span, max_slots=max_slots,
-                  resident_mb=resident_mb, steps_per_graph_replay=per_launch)
+    ttr = [inf["t_done"] - (c0 + arrivals[i]) for i, inf in enumerate(infos)]
+    span = max(inf["t_done"] for inf in infos) - (c0 + arrivals[0])
+    summary = dict(analyses_per_s=n / span, p50_s=pct(ttr, 50), p99_s=pct(ttr, 99),
+                   makespan_s=span, max_slots=max_slots,
+                   arena_mb=arena_bytes / (1 << 20), resident_mb=resident_mb,
+                   peak_residents=peak_overlap([(inf["t_admit"], inf["t_done"])
+                                                for inf in infos]),
+                   steps_per_graph_replay=per_launch)
+    return summary, [results[t][1] for t in tickets]
+
+
+def run_serving(X, W, ctx, n, rate, steps, S, seed, max_slots, per_launch,
+                plain_leg=True, resident_mb=0.0, memory_leg=True):
+    """Continuous batching vs one analysis at a time on the same arrival
+    trace; returns both summaries, the largest difference between any
+    served result and its one-at-a-time run, and (memory_leg) a served leg
+    whose arena, not the slot count, limits admission."""
+    reqs = serving_requests(X, W, ctx, n, seed)
+    arrivals = W.arrival_times(n, rate, seed)
+    foot = [X.request_footprint(p, y, S, steps) for p, y in reqs]
+    # ---- served: slots limit admission (the arena holds every request)
+    served, outs = serve(X, reqs, arrivals, S, steps, seed, max_slots,
+                         per_launch, max(sum(sorted(foot)[-max_slots:]) * 1.25,
+                                         1 << 28), resident_mb)
     log(f"[bench] served: {served}")
+    res = dict(workload=(f"serving mix: {n} analyses, Poisson arrivals at "
+                         f"{rate:g}/s, N in [2000,12000], K in [20,300], "
+                         f"20-80 peaks/phase, S={S}, c=8, {steps} steps each"),
+               served=served,
+               footprint_mb=dict(mean=float(np.mean(foot)) / (1 << 20),
+                                 max=float(np.max(foot)) / (1 << 20)))
+    if memory_leg:
+        # arena for about eight mean-sized residents, sixteen slots
+        mem_bytes = max(8 * float(np.mean(foot)), float(np.max(foot))) * 1.02
+        mem, outs_m = serve(X, reqs, arrivals, S, steps, seed, max_slots,
+                            per_launch, mem_bytes)
+        log(f"[bench] served, arena-limited: {mem}")
+        res["served_arena_limited"] = mem
+        res["max_abs_diff_arena_limited_vs_served"] = float(max(
+            np.max(np.abs(a[k] - b[k])) for a, b in zip(outs, outs_m)
+            for k in ("loc", "logscale", "trace")))
     if not plain_leg:
-        return dict(served=served)
+        return res
     # ---- plain: one at a time, per-step launches, same kernels and noise keys
-    done, ttr_p = [], []
+    done, ttr_p, plain_outs = [], [], []
     t0 = time.perf_counter()
-    first = None
     for i, (p, y) in enumerate(reqs):
         while time.perf_counter() - t0 < arrivals[i]:
             time.sleep(0.0002)
-        out = X.xrdvi_plain_run(ctx, p, y, S, steps, seed + i)
+        plain_outs.append(X.xrdvi_plain_run(ctx, p, y, S, steps, seed + i))
         t = time.perf_counter() - t0
         ttr_p.append(t - arrivals[i])
         done.append(t)
-        if first is None:
-            first = out
         if (i + 1) % 64 == 0:
             log(f"[bench] plain: {i + 1}/{n} done at {t:.1f} s")
     span_p = done[-1] - arrivals[0]
     plain = dict(analyses_per_s=n / span_p, p50_s=pct(ttr_p, 50),
                  p99_s=pct(ttr_p, 99), makespan_s=span_p)
     log(f"[bench] plain: {plain}")
-    same = float(np.max(np.abs(results[tickets[0]][1]["loc"] - first["loc"])))
-    return dict(workload=(f"serving mix: {n} analyses, Poisson arrivals at "
-                          f"{rate:g}/s, N in [2000,12000], K in [20,300], "
-                          f"20-80 peaks/phase, S={S}, c=8, {steps} steps each"),
-                served=served, plain=plain,
-                speedup_analyses_per_s=served["analyses_per_s"] / plain["analyses_per_s"],
-                max_abs_diff_first_result_vs_plain=same)
+    diff = {k: float(max(np.max(np.abs(a[k] - b[k]))
+                         for a, b in zip(outs, plain_outs)))
+            for k in ("loc", "logscale", "trace")}
+    res.update(plain=plain,
+               speedup_analyses_per_s=served["analyses_per_s"] / plain["analyses_per_s"],
+               max_abs_diff_all_vs_plain=max(diff.values()),
+               max_abs_diff_all_vs_plain_by_output=diff,
+               results_compared=len(outs))
+    return res
 
 
 def main(argv=None):
@@ -306,6 +389,11 @@ def main(argv=None):
                     action="store_false",
                     help="serve only (skip the one-at-a-time comparison)")
     ap.add_argument("--steps-per-launch", type=int, default=10)
+    ap.add_argument("--only", default="",
+                    help="comma-separated legs to run instead of all, for "
+                         "profiling: dense, windowed, asym, sec, db2000, "
+                         "background, hmc, serving (no JSON line unless "
+                         "dense runs)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print("bench.py measures one GPU only: the path runs on a single "
@@ -326,35 +414,53 @@ def main(argv=None):
     S = int(cfg["S"])
     prob = W.make_problem(WORKLOAD, SEED)
 
-    log(f"[bench] dense c=0: N={prob.N} K={prob.K} T={prob.total_peaks} S={S}")
-    dense = run_gpu(X, W, ctx, prob, S, 0.0, a.steps, a.warmup, False)
-    log(f"[bench] dense done: {dense['wall_s'] / a.steps * 1e3:.3f} ms/step")
-    log("[bench] windowed c=8")
-    win = run_gpu(X, W, ctx, prob, S, 8.0, a.steps, a.warmup, True)
-    log(f"[bench] windowed done: {win['wall_s'] / a.steps * 1e3:.3f} ms/step")
-    log("[bench] asymmetric peaks, dense c=0")
-    asym = run_gpu(X, W, ctx, prob, S, 0.0, a.steps, a.warmup, False,
-                   asymmetric=True)
-    log(f"[bench] asymmetric done: {asym['wall_s'] / a.steps * 1e3:.3f} ms/step")
-    log("[bench] sec width law, dense c=0")
-    sec = run_gpu(X, W, ctx, prob, S, 0.0, a.steps, a.warmup, False,
-                  width_law="sec")
-    log(f"[bench] sec law done: {sec['wall_s'] / a.steps * 1e3:.3f} ms/step")
-
-    log("[bench] database screening: db2000, c=8")
-    db = W.make_problem("db2000", SEED)
-    dbr = run_gpu(X, W, ctx, db, int(W.WORKLOADS["db2000"]["S"]), 8.0,
-                  max(2, a.steps // 5), 2, True)
-    log(f"[bench] db2000 done: {dbr['wall_s'] / max(2, a.steps // 5) * 1e3:.3f} ms/step")
-
-    log("[bench] background (asymmetric least squares)")
-    bg_ctx = run_background(X, W, ctx, prob)
-
-    hmc_ctx = None
-    if a.hmc:
+    legs = set(x for x in a.only.split(",") if x) or {
+        "dense", "windowed", "asym", "sec", "db2000", "background", "hmc",
+        "serving"}
+    if not a.hmc:
+        legs.discard("hmc")
+    if a.serving <= 0:
+        legs.discard("serving")
+    dense = win = asym = sec = dbr = bg_ctx = hmc_ctx = None
+    if "dense" in legs:
+        log(f"[bench] dense c=0: N={prob.N} K={prob.K} T={prob.total_peaks} S={S}")
+        dense = run_gpu(X, W, ctx, prob, S, 0.0, a.steps, a.warmup, False)
+        log(f"[bench] dense done: {dense['wall_s'] / a.steps * 1e3:.3f} ms/step")
+    if "windowed" in legs:
+        log("[bench] windowed c=8")
+        win = run_gpu(X, W, ctx, prob, S, 8.0, a.steps, a.warmup, True)
+        log(f"[bench] windowed done: {win['wall_s'] / a.steps * 1e3:.3f} ms/step")
+    if "asym" in legs:
+        log("[bench] asymmetric peaks, dense c=0")
+        asym = run_gpu(X, W, ctx, prob, S, 0.0, a.steps, a.warmup, False,
+                       asymmetric=True)
+        log(f"[bench] asymmetric done: {asym['wall_s'] / a.steps * 1e3:.3f} ms/step")
+    if "sec" in legs:
+        log("[bench] sec width law, dense c=0")
+        sec = run_gpu(X, W, ctx, prob, S, 0.0, a.steps, a.warmup, False,
+                      width_law="sec")
+        log(f"[bench] sec law done: {sec['wall_s'] / a.steps * 1e3:.3f} ms/step")
+    if "db2000" in legs:
+        log("[bench] database screening: db2000, c=8")
+        db = W.make_problem("db2000", SEED)
+        dbr = run_gpu(X, W, ctx, db, int(W.WORKLOADS["db2000"]["S"]), 8.0,
+                      max(2, a.steps // 5), 2, True)
+        log(f"[bench] db2000 done: {dbr['wall_s'] / max(2, a.steps // 5) * 1e3:.3f} ms/step")
+    if "background" in legs:
+        log("[bench] background (asymmetric least squares)")
+        bg_ctx = run_background(X, W, ctx, prob)
+    if "hmc" in legs:
         log("[bench] hmc: 1000 warm-up + 1000 kept iterations")
         hmc_ctx = run_hmc(X, W, ctx, prob)
         log(f"[bench] hmc done: {hmc_ctx['hmc_s']:.2f} s")
+    if dense is None or not {"windowed", "asym", "sec", "db2000"} <= legs:
+        if "serving" in legs:
+            log(f"[bench] serving: {a.serving} analyses")
+            run_serving(X, W, ctx, a.serving, a.serving_rate, a.serving_steps,
+                        32, 4000, a.max_slots, a.steps_per_launch,
+                        a.serving_plain, a.resident_mb)
+        log("[bench] partial run (--only): no JSON line")
+        return 0
 
     ms_step = dense["wall_s"] / a.steps * 1e3
     value = sum(dense["points"]) / dense["wall_s"]
@@ -391,6 +497,8 @@ def main(argv=None):
             "kernel_ms": dense["kernel_ms"],
             "flops_per_peak_point": FLOPS_PER_PEAK_POINT,
             "peak_points_per_launch": pts_launch,
+            "counters": counter_rates(profsummary.recorded(DENSE_KERNEL),
+                                      dense["kernel_ms"]),
         },
         "windowed_c8": {
             "value": sum(win["points"]) / win["wall_s"],
@@ -435,7 +543,7 @@ def main(argv=None):
             "mcmc_full_analysis_s": 1326.9,
         },
     }
-    if a.serving > 0:
+    if "serving" in legs:
         log(f"[bench] serving: {a.serving} analyses")
         out["serving"] = run_serving(X, W, ctx, a.serving, a.serving_rate,
                                      a.serving_steps, 32, 4000, a.max_slots,

@@ -37,9 +37,10 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic(kernel: str):
-    """Calibrated HBM bytes per dispatch recorded for `kernel` under
-    profiles/, or None when none was recorded for the current sources."""
+def recorded(kernel: str):
+    """The profile record of `kernel` under profiles/ (calibrated HBM bytes,
+    executed FP32 flops and VALU instruction counts per dispatch), or None
+    when none was recorded for the current kernel sources."""
     want = kernel_sources_sha256()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(path) as f:
@@ -47,8 +48,14 @@ def recorded_traffic(kernel: str):
                 if line.startswith(RECORD_PREFIX):
                     rec = json.loads(line[len(RECORD_PREFIX):])
                     if rec.get("kernel") == kernel and rec.get("sources_sha256") == want:
-                        return float(rec["bytes_per_dispatch"])
+                        return rec
     return None
+
+
+def recorded_traffic(kernel: str):
+    """Calibrated HBM bytes per dispatch recorded for `kernel`, or None."""
+    rec = recorded(kernel)
+    return None if rec is None else float(rec["bytes_per_dispatch"])
 
 
 def _stats(path):
@@ -143,9 +150,25 @@ def summarize(out, title, cmd, stats_csv, fetch=None, write=None, cfetch=None,
     if extra:
         L += ["", extra]
     if record is not None:
-        L += ["", RECORD_PREFIX + json.dumps(dict(
-            kernel=record_kernel, bytes_per_dispatch=round(record),
-            sources_sha256=kernel_sources_sha256()))]
+        rec = dict(kernel=record_kernel, bytes_per_dispatch=round(record))
+        # executed FP32 flops and the VALU instruction mix of the recorded
+        # kernel, for the benchmark's counter-measured rates
+        for path, names in ((flops, ("ADD", "MUL", "FMA", "TRANS")), (sq, ())):
+            if not path:
+                continue
+            c = _counters(path)
+            k = next((k for k, _ in c if short(k) == record_kernel), None)
+            if k is None:
+                continue
+            if names:
+                v = {n: c.get((k, f"SQ_INSTS_VALU_{n}_F32"), (0, 0.0))[1] for n in names}
+                rec["flops_per_dispatch"] = round(
+                    64 * (v["ADD"] + v["MUL"] + 2 * v["FMA"] + v["TRANS"]))
+                rec["valu_trans_per_dispatch"] = round(v["TRANS"])
+            elif (k, "SQ_INSTS_VALU") in c:
+                rec["valu_per_dispatch"] = round(c[(k, "SQ_INSTS_VALU")][1])
+        rec["sources_sha256"] = kernel_sources_sha256()
+        L += ["", RECORD_PREFIX + json.dumps(rec)]
     with open(out, "w") as fh:
         fh.write("\n".join(L) + "\n")
 
