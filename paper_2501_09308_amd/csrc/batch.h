@@ -14,7 +14,7 @@ constexpr int kMaxSlots = 512;
 // (windowed or dense, symmetric or asymmetric peaks, constant or sec-law
 // width), so that each kernel keeps the register budget of its
 // single-analysis counterpart.
-enum BatchKind { kSample = 0, kWindows, kWindowsSec, kPlan, kPlanSec,
+enum BatchKind { kSample = 0, kWindows, kWindowsSec, kPlan, kPlanSec, kCandExt, kCand,
                  kFusedWin, kFusedDense, kFusedWinAsym, kFusedDenseAsym,
                  kFusedWinSec, kFusedDenseSec, kFusedWinAsymSec,
                  kFusedDenseAsymSec,
@@ -64,6 +64,10 @@ inline void batch_units(const ProbDev &P, int S, int units[kKinds]) {
         units[sec ? kWindowsSec : kWindows] = (int)(((long long)S * P.T + 255) / 256);
     if (!win)   // the windowed forward tile finds its own ranges
         units[sec ? kPlanSec : kPlan] = (int)(((long long)S * P.ntiles * P.K + 255) / 256);
+    if (win && !sec) {   // ... among candidates found once per step
+        units[kCandExt] = (P.K + kWave - 1) / kWave;
+        units[kCand] = (int)(((long long)P.K + kCandThreads - 1) / kCandThreads) * P.ntiles;
+    }
     units[fused_kind(win, asym, sec)] = P.ntiles * S;
     if (win) units[adjoint_kind(asym, sec)] = P.K * S;
     units[kElbo] = 1;

@@ -119,6 +119,37 @@ __global__ __launch_bounds__(256) void kb_plan(const SlotDev *tab,
     }
 }
 
+__global__ __launch_bounds__(kCandThreads) void kb_cand_ext(const SlotDev *tab,
+                                                            const SchedDev *sch) {
+    __shared__ PrefixSmem ps;
+    __shared__ CandExtSmem sm;
+    load_prefix(sch, kCandExt, ps);
+    const int total = uniform(ps.pre[ps.n]);
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int i = find_slot(ps, u);
+        const SlotDev &d = slot_entry(tab, ps, i);
+        if (!running(d) || !d.st.cab) continue;
+        cand_ext_block(d.P, d.st, d.st.phi, local_unit(ps, i, u) * kWave, sm);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kCandThreads) void kb_cand(const SlotDev *tab,
+                                                        const SchedDev *sch) {
+    __shared__ PrefixSmem ps;
+    load_prefix(sch, kCand, ps);
+    const int total = uniform(ps.pre[ps.n]);
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int i = find_slot(ps, u);
+        const SlotDev &d = slot_entry(tab, ps, i);
+        if (!running(d) || !d.st.cab) continue;
+        const int local = local_unit(ps, i, u);
+        const int nkb = (d.P.K + kCandThreads - 1) / kCandThreads;
+        const int t = local / nkb, k = (local % nkb) * kCandThreads + threadIdx.x;
+        if (t < d.P.ntiles && k < d.P.K) cand_elem(d.P, d.st, t, k);
+    }
+}
+
 template <bool WIN, bool ASYM, bool SEC>
 __global__ __launch_bounds__(kBlock) void kb_fused(const SlotDev *tab,
                                                    const SchedDev *sch) {
@@ -219,6 +250,8 @@ hipError_t launch_batch_step(const SlotDev *tab, const SchedDev *sch,
     if (sec) kb_windows<true><<<kGridLarge, 256, 0, s>>>(tab, sch);
     kb_plan<false><<<kGridLarge, 256, 0, s>>>(tab, sch);
     if (sec) kb_plan<true><<<kGridLarge, 256, 0, s>>>(tab, sch);
+    kb_cand_ext<<<kGridSmall, kCandThreads, 0, s>>>(tab, sch);
+    kb_cand<<<kGridLarge, kCandThreads, 0, s>>>(tab, sch);
     kb_fused<true, false, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
     kb_fused<false, false, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
     kb_fused<true, true, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);

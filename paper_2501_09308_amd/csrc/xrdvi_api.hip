@@ -71,6 +71,10 @@ size_t step_bytes(const StepShape &sh) {
     b += align256(sizeof(float) * S * (size_t)sh.N);  // rres
     b += align256(sizeof(double) * NS * K * S);     // pw
     b += align256(sh.sec ? sizeof(float4) * S * (size_t)std::max(sh.T, 1) : 4);  // psec
+    const bool cand = !sh.dense && !sh.sec;
+    b += align256(cand ? sizeof(int2) * nt * K : 4);                      // cab
+    b += align256(cand ? sizeof(double) * kCandKeep * nt * K : 4);        // cp
+    b += align256(cand ? sizeof(double4) * K : 4);                        // cext
     return b;
 }
 
@@ -99,6 +103,11 @@ StepDev carve_step(void *base, const StepShape &sh) {
     st.rres = (float *)take(sizeof(float) * S * (size_t)sh.N);
     st.pw = (double *)take(sizeof(double) * NS * K * S);
     st.psec = (float4 *)take(sh.sec ? sizeof(float4) * S * (size_t)std::max(sh.T, 1) : 4);
+    const bool cand = !sh.dense && !sh.sec;
+    st.cab = (int2 *)take(cand ? sizeof(int2) * nt * K : 4);
+    st.cp = (double *)take(cand ? sizeof(double) * kCandKeep * nt * K : 4);
+    st.cext = (double4 *)take(cand ? sizeof(double4) * K : 4);
+    if (!cand) st.cab = nullptr;
     return st;
 }
 

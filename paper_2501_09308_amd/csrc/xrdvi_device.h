@@ -123,6 +123,23 @@ struct StepDev {
     double *llp;      // [S][ntiles] per-tile log-likelihood
     float *part;      // [ntiles][K][S][num_sums] adjoint tile sums
     double *sd;       // [D K] exp(logscale)
+    // windowed mode, constant width: the candidate peaks of each (tile,
+    // phase) over the step's samples, laid out [..][ntiles][K] so that the
+    // forward's threads (one per phase of a tile) read them coalesced:
+    int2 *cab;        // [ntiles][K] candidates [ca, cb)
+    double *cp;       // [kCandKeep][ntiles][K] positions of the first ones
+    double4 *cext;    // [K] (min mu, max mu, max w, max w alpha) over samples
+};
+
+// Candidate peaks [ca, cb) of one phase for one tile are those whose window
+// can reach the tile at some sample of the step; the positions of the first
+// four of them are kept beside the range, so that the windowed forward finds
+// its exact ranges without a search when a tile has at most four candidates
+// (the usual case).
+constexpr int kCandKeep = 4;
+struct CandRec {
+    int ca, cb;
+    double p[kCandKeep];
 };
 
 // Read-only view of data that no kernel of the current launch writes:
@@ -195,12 +212,16 @@ __device__ __forceinline__ double softplus(double a) {
 }
 
 // FP32 kernel constants of one (sample, phase).
-// nrm = 2 / (1 + alpha) for asymmetric peaks, 1 otherwise.
+// nrm = 2 / (1 + alpha) for asymmetric peaks, 1 otherwise.  The kernels
+// evaluate the Gaussian as 2^(-tt) = 2^(-1 - q2^2) with tt = 1 + q2^2 (the
+// Lorentzian's denominator, and the exponent's negation is free), so its
+// amplitude here is twice h (1 - r) cG n / w, and the adjoint's Gaussian
+// sums are half those of 2^(-q2^2) (phase_grad doubles them).
 __device__ __forceinline__ float4 phase_consts(double h, double mu, double w,
                                                double r, double nrm = 1.0) {
     const double iw = 1.0 / w;
     return make_float4((float)(2.0 * iw),
-                       (float)(h * (1.0 - r) * kCG * iw * nrm),
+                       (float)(2.0 * h * (1.0 - r) * kCG * iw * nrm),
                        (float)(h * r * kCL * iw * nrm), (float)mu);
 }
 __device__ __forceinline__ double asym_norm(double alpha) {
@@ -530,6 +551,149 @@ __device__ inline int2 gauss_range(const ProbDev &P, const PhaseWin &pw, int k,
     return make_int2(ga, gb);
 }
 
+// ---- candidate ranges (windowed mode, constant width) --------------------
+//
+// The peaks of a phase whose window reaches a tile at sample s lie among
+// those whose window could reach it at any sample of the step: positions p
+// with xa - max_s(mu) - c max_s(w alpha) <= p <= xb - min_s(mu) + c max_s(w)
+// (widened by a margin far above FP64 rounding).  Found once per step for
+// every (tile, phase), so that each (tile, sample) of the windowed forward
+// reads them with coalesced loads instead of searching the phase with
+// scattered ones.
+constexpr int kCandThreads = 256;
+
+// The extremes of each phase over the step's samples: (min mu, max mu,
+// max w, max w alpha) to st.cext[k].  Block of kCandThreads threads: 64
+// phases (starting at k0) times 4 slices of the samples, combined in LDS.
+struct CandExtSmem {
+    double v[4][4][kWave];
+};
+__device__ inline void cand_ext_block(const ProbDev &P, const StepDev &st,
+                                      const double *phi, int k0,
+                                      CandExtSmem &sm) {
+    const int kk = threadIdx.x % kWave, sl = threadIdx.x / kWave;
+    const int k = k0 + kk;
+    const size_t row = (size_t)P.D * P.K;
+    double mn = __builtin_huge_val(), mx = -__builtin_huge_val(), wm = 0.0, wam = 0.0;
+    if (k < P.K) {
+        for (int s = sl; s < st.S; s += 4) {
+            const double mu = phi[s * row + P.K + k], w = phi[s * row + 2 * P.K + k];
+            const double al = P.D == 5 ? phi[s * row + 4 * P.K + k] : 1.0;
+            mn = fmin(mn, mu);
+            mx = fmax(mx, mu);
+            wm = fmax(wm, w);
+            wam = fmax(wam, w * al);
+        }
+    }
+    sm.v[0][sl][kk] = mn; sm.v[1][sl][kk] = mx; sm.v[2][sl][kk] = wm; sm.v[3][sl][kk] = wam;
+    __syncthreads();
+    if (sl == 0 && k < P.K) {
+#pragma unroll
+        for (int o = 1; o < 4; ++o) {
+            mn = fmin(mn, sm.v[0][o][kk]);
+            mx = fmax(mx, sm.v[1][o][kk]);
+            wm = fmax(wm, sm.v[2][o][kk]);
+            wam = fmax(wam, sm.v[3][o][kk]);
+        }
+        st.cext[k] = make_double4(mn, mx, wm, wam);
+    }
+}
+
+// Candidate range of (tile t, phase k) from the phase's extremes.
+__device__ inline void cand_elem(const ProbDev &P, const StepDev &st, int t,
+                                 int k) {
+#pragma clang fp contract(off)
+    const double4 e = st.cext[k];
+    const double lo_off = e.y + P.cutoff * e.w;
+    const double hi_off = P.cutoff * e.z - e.x;
+    const int a = P.off[k], b = P.off[k + 1];
+    const int i0 = t * kTile, i1 = min(i0 + kTile, P.N);
+    const double xa = P.x[i0], xb = P.x[i1 - 1];
+    const double pl = xa - lo_off - (1e-9 + 1e-12 * fabs(xa));
+    const double pu = xb + hi_off + (1e-9 + 1e-12 * fabs(xb));
+    auto ge = [&](double p) { return !(p < pl); };
+    auto gt = [&](double p) { return p > pu; };
+    const Probe<4, double> pa = probe_at<4>(P.pos, a, b, tab_guess(P, k, pl, a, b));
+    const Probe<4, double> pb = probe_at<4>(P.pos, a, b, tab_guess(P, k, pu, a, b));
+    const int na = probe_count(pa, a, b, ge), nb = probe_count(pb, a, b, gt);
+    const int ca = probe_settle<4>(P.pos, a, b, pa.j0, na, ge);
+    int cb = probe_settle<4>(P.pos, a, b, pb.j0, nb, gt);
+    cb = cb < ca ? ca : cb;
+    const size_t ci = (size_t)t * P.K + k, ntk = (size_t)P.ntiles * P.K;
+    st.cab[ci] = make_int2(ca, cb);
+#pragma unroll
+    for (int q = 0; q < kCandKeep; ++q)
+        st.cp[q * ntk + ci] = ca + q < cb ? P.pos[ca + q] : 0.0;
+}
+
+// The candidates of (tile t, phase k) as the forward's staging thread reads
+// them.
+__device__ __forceinline__ CandRec cand_read(const ProbDev &P, const StepDev &st,
+                                             int t, int k) {
+    const size_t ci = (size_t)t * P.K + k, ntk = (size_t)P.ntiles * P.K;
+    CandRec r;
+    const int2 ab = st.cab[ci];
+    r.ca = ab.x;
+    r.cb = ab.y;
+#pragma unroll
+    for (int q = 0; q < kCandKeep; ++q) r.p[q] = st.cp[q * ntk + ci];
+    return r;
+}
+
+// The ranges [ja, jb) and [ga, gb) of phase_window and gauss_range
+// (constant width), searched within the candidates [ca, cb) of the tile:
+// from the candidates' own positions when there are at most four, else by
+// the batched searches restricted to the candidates.  The predicates are
+// those of phase_window and gauss_range, monotone over the phase, so the
+// ranges are the same as from searches over the whole phase.
+__device__ inline PhaseWin phase_window_cand(const ProbDev &P, const double *ph,
+                                             int k, double xa, double xb,
+                                             const CandRec &cand, int2 *gr) {
+#pragma clang fp contract(off)
+    PhaseWin r;
+    r.a = P.off[k];
+    r.b = P.off[k + 1];
+    r.mu = ph[P.K + k];
+    r.w = ph[2 * P.K + k];
+    r.alpha = P.D == 5 ? ph[4 * P.K + k] : 1.0;
+    r.g_mono = true;
+    const double mu = r.mu, w = r.w, alpha = r.alpha;
+    const int ca = cand.ca, cb = cand.cb;
+    auto reach_a = [&](double p) { return xa <= window_bounds<false>(P, p, mu, w, alpha).y; };
+    auto past_b = [&](double p) { return window_bounds<false>(P, p, mu, w, alpha).x > xb; };
+    auto g_a = [&](double p) { return p >= xa - mu - kGaussReach * w * alpha; };
+    auto g_b = [&](double p) { return p > xb - mu + kGaussReach * w; };
+    int ja, jb, ga, gb;
+    if (cb - ca <= kCandKeep) {
+        Probe<kCandKeep, double> pr;
+        pr.j0 = ca;
+#pragma unroll
+        for (int q = 0; q < kCandKeep; ++q) pr.v[q] = cand.p[q];
+        ja = ca + probe_count(pr, ca, cb, reach_a);
+        jb = ca + probe_count(pr, ca, cb, past_b);
+        ga = ca + probe_count(pr, ca, cb, g_a);
+        gb = ca + probe_count(pr, ca, cb, g_b);
+    } else {
+        const double hw = P.cutoff * w, hwu = P.D == 5 ? hw * alpha : hw;
+        const double rg = kGaussReach * w, rgu = rg * alpha;
+        ja = probe_result<4>(P.pos, ca, cb, probe_at<4>(P.pos, ca, cb,
+                             tab_guess(P, k, xa - mu - hwu, ca, cb)), reach_a);
+        jb = probe_result<4>(P.pos, ca, cb, probe_at<4>(P.pos, ca, cb,
+                             tab_guess(P, k, xb - mu + hw, ca, cb)), past_b);
+        ga = probe_result<4>(P.pos, ca, cb, probe_at<4>(P.pos, ca, cb,
+                             tab_guess(P, k, xa - mu - rgu, ca, cb)), g_a);
+        gb = probe_result<4>(P.pos, ca, cb, probe_at<4>(P.pos, ca, cb,
+                             tab_guess(P, k, xb - mu + rg, ca, cb)), g_b);
+    }
+    if (jb < ja) jb = ja;
+    ga = ga < ja ? ja : (ga > jb ? jb : ga);
+    gb = gb < ga ? ga : (gb > jb ? jb : gb);
+    r.ja = ja;
+    r.jb = jb;
+    *gr = make_int2(ga, gb);
+    return r;
+}
+
 // Range entry of (sample s, tile t, phase k); phi: [S][D][K].  For
 // asymmetric peaks *side receives (jr, jl) with ga <= jr <= jl <= gb.
 // Ranges may be wider than needed (the windowed kernels mask each peak by
@@ -704,8 +868,8 @@ __device__ __forceinline__ SegQ seg_q(const PeakRec &r, float u,
 }
 
 // Forward terms of the peaks [j0, j1) of one phase: accL += I l, accG += I e
-// (GAUSS) with l = 1 / (1 + q2^2), e = 2^(-q2^2); GAUSS segments take the
-// near form of q2.
+// (GAUSS) with l = 1 / (1 + q2^2), e = 2^(-1 - q2^2) (see phase_consts);
+// GAUSS segments take the near form of q2.
 template <bool WIN, bool GAUSS, int SIDE, bool SEC, typename PK>
 __device__ __forceinline__ void fwd_segment(const PK &pk, int j0, int j1,
                                             const int (&idx)[kPPL],
@@ -725,13 +889,13 @@ __device__ __forceinline__ void fwd_segment(const PK &pk, int j0, int j1,
             const float q2 = seg_q<SIDE, GAUSS, SEC>(r, u[p], pp, p, iw2, iw2r).q2;
             const float tt = mk.apply(idx[p], fmaf(q2, q2, 1.0f));
             accL[p] = fmaf(I, rcp_f32(tt), accL[p]);
-            if (GAUSS) accG[p] = fmaf(I, exp2_f32(1.0f - tt), accG[p]);
+            if (GAUSS) accG[p] = fmaf(I, exp2_f32(-tt), accG[p]);
         }
     }
 }
 
 // Per point and phase: l0 = sum I l, l1 = sum I l^2 q2, l2 = sum I l^2,
-// e0 = sum I e, e1 = sum I e q2, e2 = sum I e q2^2 (e = 2^(-q2^2),
+// e0 = sum I e, e1 = sum I e q2, e2 = sum I e q2^2 (e = 2^(-1 - q2^2),
 // l = 1/(1 + q2^2)).
 struct Acc6 {
     float l0[kPPL], l1[kPPL], l2[kPPL], e0[kPPL], e1[kPPL], e2[kPPL];
@@ -788,7 +952,7 @@ __device__ __forceinline__ void adj_segment(const SegPeaks &pk, int j0, int j1,
             const float Ill = Il * l;
             float Ie = 0.f, Ieq = 0.f;
             if (GAUSS) {
-                Ie = I * exp2_f32(1.0f - tt);
+                Ie = I * exp2_f32(-tt);
                 Ieq = Ie * q2;
             }
             if (SIDE != kBoth) {
@@ -1158,7 +1322,10 @@ __device__ void win_phase_global(const SegPeaks &sp, int4 r, int2 r2,
 
 // One staged record's terms at the lane's points (a: centre, scale below,
 // Lorentzian and Gaussian amplitudes; b: window, the scale above and, with
-// the Gaussian, the centre's rounding error).
+// the Gaussian, the centre's rounding error).  Symmetric records hold the
+// centre times the scale in place of the centre when they have no Gaussian,
+// and the centre's rounding error times the scale when they have one, so
+// that q2 takes fused multiply-adds.
 template <bool ASYM, bool GAUSS>
 __device__ __forceinline__ void win_record(const float4 a, const WinRec2<ASYM> b,
                                            const float (&u)[kPPL],
@@ -1174,12 +1341,21 @@ __device__ __forceinline__ void win_record(const float4 a, const WinRec2<ASYM> b
         // tile the window misses is skipped by the whole wave
         const int ii = WinRec2<ASYM>::template rel<GAUSS>() ? idx[p] - i0 : idx[p];
         if ((unsigned)(ii - wnd.x) < (unsigned)wnd.y) {
-            float d = u[p] - a.x;
-            if (GAUSS) d += ul[p] - cl;
-            const float q2 = d * (ASYM ? (d >= 0.f ? ah : a.y) : a.y);
+            float q2;
+            if (ASYM) {
+                float d = u[p] - a.x;
+                if (GAUSS) d += ul[p] - cl;
+                q2 = d * (d >= 0.f ? ah : a.y);
+            } else if (GAUSS) {
+                // (u - centre) s + (ul s - cl s), cl s kept in the record
+                q2 = fmaf(u[p] - a.x, a.y, fmaf(ul[p], a.y, -cl));
+            } else {
+                // u s - centre s, centre s kept in the record (far peaks)
+                q2 = fmaf(u[p], a.y, -a.x);
+            }
             const float tt = fmaf(q2, q2, 1.0f);
             sig[p] = fmaf(a.z, rcp_f32(tt), sig[p]);
-            if (GAUSS) sig[p] = fmaf(a.w, exp2_f32(1.0f - tt), sig[p]);
+            if (GAUSS) sig[p] = fmaf(a.w, exp2_f32(-tt), sig[p]);
         }
     }
 }
@@ -1250,8 +1426,15 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
         if (tid < nk) {
             cst = pkv[c0 + tid];
             if (ASYM) iw2r = pkrv[c0 + tid];
-            pw = phase_window<SEC>(P, ph, c0 + tid, i0, i1, wlo, whi);
-            gr = gauss_range<SEC>(P, pw, c0 + tid, xa, xb);
+            if constexpr (!SEC) {
+                // constant width: among the step's candidates (written by
+                // the candidate kernel before this one)
+                pw = phase_window_cand(P, ph, c0 + tid, xa, xb,
+                                       cand_read(P, st, t, c0 + tid), &gr);
+            } else {
+                pw = phase_window<SEC>(P, ph, c0 + tid, i0, i1, wlo, whi);
+                gr = gauss_range<SEC>(P, pw, c0 + tid, xa, xb);
+            }
         }
         const int cnt = pw.jb - pw.ja, cg = gr.y - gr.x;
         // inclusive prefixes over the block of the record counts and of the
@@ -1275,22 +1458,15 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
             const float iw2 = cst.x, aG = cst.y, aL = cst.z;
             // The tile-relative centre comes from the FP64 position and
             // shift (rounded once, its rounding error kept for the records
-            // with the Gaussian), the window from the window step's
-            // own bounds and grid search (constant width), and the side of
-            // an asymmetric peak from the predicates of the tile plan's side
-            // searches.
+            // with the Gaussian), the window from the window step's arrays
+            // (a load instead of a search: the forward is bound by VALU
+            // issue), and the side of an asymmetric peak from the predicates
+            // of the tile plan's side searches.
             for (int q = 0; q < cnt; ++q) {
                 const int j = pw.ja + q;
                 const double pj = P.pos[j];
                 const float I = SEC ? psec[4 * j + 1] : P.inten[j];
                 const float c = SEC ? psec[4 * j] : 1.f;
-                // (under the sec law the window step's own windows: forming
-                // them here would take a cosine per record)
-                GridProbe gp{};
-                if (!SEC) {
-                    const double2 ab = window_bounds<SEC>(P, pj, pw.mu, pw.w, pw.alpha);
-                    gp = grid_probe(P.x, P.N, P.x0, P.inv_dx, ab.x, ab.y);
-                }
                 float alo = iw2 * c, ahi = alo;
                 if (ASYM) {
                     // centre at or below the tile's first point: the tile
@@ -1306,10 +1482,16 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
                                              (j < gr.x ? j - pw.ja : q - cg);
                 const double cx = (pj - xref) + pw.mu;
                 const float cxf = (float)cx;
-                sm.rec[slot] = make_float4(cxf, alo, I * aL, gauss ? I * aG : 0.f);
-                const int2 wnd = SEC ? make_int2(wlo[j], whi[j]) : grid_finish(P.x, P.N, gp);
+                // symmetric peaks keep the centre times the scale (records
+                // without the Gaussian) or the rounding error of the centre
+                // times the scale (with it), so that q2 takes fused
+                // multiply-adds (see win_record)
+                sm.rec[slot] = make_float4(ASYM || gauss ? cxf : (float)(cx * (double)alo),
+                                           alo, I * aL, gauss ? I * aG : 0.f);
+                const int2 wnd = make_int2(wlo[j], whi[j]);
                 const int whi_j = wnd.y < wnd.x ? wnd.x : wnd.y;
-                const float cl = (float)(cx - (double)cxf);
+                const double cld = cx - (double)cxf;
+                const float cl = (float)(ASYM ? cld : cld * (double)alo);
                 sm.rec2[slot] = gauss
                     ? WinRec2<ASYM>::template make<true>(wnd.x, whi_j, i0, ahi, cl)
                     : WinRec2<ASYM>::template make<false>(wnd.x, whi_j, i0, ahi, cl);
@@ -1418,7 +1600,7 @@ __device__ __forceinline__ void adj_point_G(const AdjPt &pt, float c,
                                             const SecW &wl, const SecW &wh,
                                             float (&acc)[ASYM ? 12 : 6]) {
     const float q2 = pt.q2, tt = pt.tt;
-    const float Re = pt.R * exp2_f32(1.0f - tt);
+    const float Re = pt.R * exp2_f32(-tt);
     const float Req = Re * q2;
     float m1G;
     if (SEC) {

@@ -86,6 +86,19 @@ __global__ void k_plan(ProbDev P, StepDev st, const double *__restrict__ phi) {
         plan_elem<SEC>(P, st, phi, g);
 }
 
+// a2 (windowed, constant width): the phases' extremes over the samples,
+// grid ceil(K / 64); then the candidate ranges, grid (ceil(K / 256),
+// ntiles), one thread per (tile, phase).
+__global__ __launch_bounds__(kCandThreads) void k_cand_ext(ProbDev P, StepDev st,
+                                                           const double *__restrict__ phi) {
+    __shared__ CandExtSmem sm;
+    cand_ext_block(P, st, phi, blockIdx.x * kWave, sm);
+}
+__global__ __launch_bounds__(kCandThreads) void k_cand(ProbDev P, StepDev st) {
+    const int k = blockIdx.x * kCandThreads + threadIdx.x;
+    if (k < P.K) cand_elem(P, st, blockIdx.y, k);
+}
+
 // a3 + a4 (+ a6): grid (ntiles, S), kBlock threads, blocks ordered by XCD
 // (the samples of a tile share its positions and counts in one L2, and
 // their adjoint partials, adjacent in memory, merge there before write-back).
@@ -215,10 +228,19 @@ hipError_t launch_peak_plan(const ProbDev &P, const StepDev &st,
                           st.hi, nullptr, stream, P.sec ? st.psec : nullptr);
 }
 
-// Dense mode only: the windowed forward tile finds its own ranges.
+// Dense mode: the tile plan.  Windowed mode with a constant width: the
+// candidate ranges of each (tile, phase) over the step's samples (the
+// windowed forward tile then finds its exact ranges among them).
 hipError_t launch_plan(const ProbDev &P, const StepDev &st, const double *phi,
                        hipStream_t stream) {
-    if (P.cutoff > 0.0) return hipSuccess;
+    if (P.cutoff > 0.0) {
+        if (!P.sec && st.cab) {
+            k_cand_ext<<<(P.K + kWave - 1) / kWave, kCandThreads, 0, stream>>>(P, st, phi);
+            dim3 g((P.K + kCandThreads - 1) / kCandThreads, P.ntiles);
+            k_cand<<<g, kCandThreads, 0, stream>>>(P, st);
+        }
+        return hipGetLastError();
+    }
     const size_t n = (size_t)st.S * P.ntiles * P.K;
     size_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;

@@ -228,14 +228,18 @@ __device__ inline void phase_grad(const ProbDev &P, const double *E, double h,
                                   double w, double r, double alpha,
                                   double g[5]) {
 #pragma clang fp contract(off)
+    // the Gaussian sums E[0..2] (E[6..8]) were accumulated with
+    // 2^(-1 - q2^2), half the Gaussian's 2^(-q2^2): doubled here (exactly)
     double E0, E1, E2, L0, L1, L2, nrm = 1.0;
     if (P.D == 5) {
         const double ia = 1.0 / alpha;
-        E0 = E[0] + E[6];  E1 = E[1] + ia * E[7];  E2 = E[2] + E[8];
+        E0 = 2.0 * (E[0] + E[6]);  E1 = 2.0 * (E[1] + ia * E[7]);
+        E2 = 2.0 * (E[2] + E[8]);
         L0 = E[3] + E[9];  L1 = E[4] + ia * E[10]; L2 = E[5] + E[11];
         nrm = asym_norm(alpha);
     } else {
-        E0 = E[0]; E1 = E[1]; E2 = E[2]; L0 = E[3]; L1 = E[4]; L2 = E[5];
+        E0 = 2.0 * E[0]; E1 = 2.0 * E[1]; E2 = 2.0 * E[2];
+        L0 = E[3]; L1 = E[4]; L2 = E[5];
     }
     const double iw = 1.0 / w, iw2 = iw * iw;
     const double cg = (1.0 - r) * kCG * nrm, cl = r * kCL * nrm;
@@ -244,7 +248,7 @@ __device__ inline void phase_grad(const ProbDev &P, const double *E, double h,
     g[2] = h * iw2 * (cg * (2.0 * kLn2 * E2 - E0) + cl * (L0 - 2.0 * L2));
     g[3] = h * iw * nrm * (kCL * L0 - kCG * E0);
     if (P.D == 5) {
-        const double E2u = E[8], Q2u = E[9] - E[11];
+        const double E2u = 2.0 * E[8], Q2u = E[9] - E[11];
         g[4] = h * iw * (-(cg * E0 + cl * L0) / (1.0 + alpha)
                          + (cg * 2.0 * kLn2 * E2u + cl * 2.0 * Q2u) / alpha);
     }
