@@ -456,9 +456,10 @@ def main(argv=None):
     if dense is None or not {"windowed", "asym", "sec", "db2000"} <= legs:
         if "serving" in legs:
             log(f"[bench] serving: {a.serving} analyses")
-            run_serving(X, W, ctx, a.serving, a.serving_rate, a.serving_steps,
-                        32, 4000, a.max_slots, a.steps_per_launch,
-                        a.serving_plain, a.resident_mb)
+            r = run_serving(X, W, ctx, a.serving, a.serving_rate, a.serving_steps,
+                            32, 4000, a.max_slots, a.steps_per_launch,
+                            a.serving_plain, a.resident_mb)
+            log("[bench] serving: " + json.dumps(r, default=float))
         log("[bench] partial run (--only): no JSON line")
         return 0
 

@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kCandThreads) void kb_cand(const SlotDev *tab,
 template <bool WIN, bool ASYM, bool SEC>
 __global__ __launch_bounds__(kBlock) void kb_fused(const SlotDev *tab,
                                                    const SchedDev *sch) {
-    using Smem = typename std::conditional<WIN, WinSmem<ASYM, kWinPeaksBatched>,
+    using Smem = typename std::conditional<WIN, WinSmem<ASYM>,
                                            FusedSmem>::type;
     __shared__ PrefixSmem ps;
     __shared__ Smem sm;

@@ -1215,12 +1215,13 @@ __device__ void fused_tile(const ProbDev &P, const StepDev &st, int t, int s,
 // fit the staging space (they come last in the chunk) are evaluated from
 // global memory, phase by phase.
 constexpr int kWinChunk = kBlock;   // phases staged at a time (one per thread)
-// Staged peak records per chunk: 768 (21 KB of LDS, seven blocks per CU)
-// for the single-analysis forward; 1024 for the batched one, whose registers
-// already hold it to four blocks per CU and whose larger analyses would
-// otherwise spill more phases to the global-memory path.
-constexpr int kWinPeaks = 768;
-constexpr int kWinPeaksBatched = 1024;
+// LDS for the staged peak records of a chunk, the same for the
+// single-analysis and the batched forward: which phases take the
+// global-memory path, and so the order in which a point's terms are summed,
+// depends on it, and a served analysis gives the same bits as its
+// one-at-a-time run only if both kernels stage alike.  24 KB hold 1024
+// symmetric or 768 asymmetric records (six blocks per CU).
+constexpr int kWinRecBytes = 21 * 1024;
 
 // Second word of a staged record.  The record's FP32 centre relative to the
 // tile is rounded; records whose Gaussian reaches the tile also carry that
@@ -1271,14 +1272,23 @@ struct WinRec2<true> {
     __device__ __forceinline__ float cl() const { return cl_; }
 };
 
-template <bool ASYM, int CAP = kWinPeaks>
+template <bool ASYM>
 struct WinSmem {
-    static constexpr int kCap = CAP;
-    float4 rec[CAP];                // (centre, 2c/(Aw) below, amp L, amp G)
-    WinRec2<ASYM> rec2[CAP];        // window[, 2c/(alpha w)], centre's error
+    static constexpr int kCap = kWinRecBytes / (sizeof(float4) + sizeof(WinRec2<ASYM>));
+    struct Staged {
+        float4 rec[kCap];           // (centre, 2c/(Aw) below, amp L, amp G)
+        WinRec2<ASYM> rec2[kCap];   // window[, 2c/(alpha w)], centre's error
+    };
+    struct Sums {
+        float sig[kWaves][kTile];   // the waves' partial sums at the points
+        float rres[kTile];
+    };
+    // the last chunk's records are consumed before the sums are written
+    union {
+        Staged r;
+        Sums e;
+    };
     int wmax[kWaves], wmaxn[kWaves], wcnt[kWaves], wcntg[kWaves];
-    float sig[kWaves][kTile];
-    float rres[kTile];
     double red[kWaves];
 };
 
@@ -1486,13 +1496,13 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
                 // without the Gaussian) or the rounding error of the centre
                 // times the scale (with it), so that q2 takes fused
                 // multiply-adds (see win_record)
-                sm.rec[slot] = make_float4(ASYM || gauss ? cxf : (float)(cx * (double)alo),
+                sm.r.rec[slot] = make_float4(ASYM || gauss ? cxf : (float)(cx * (double)alo),
                                            alo, I * aL, gauss ? I * aG : 0.f);
                 const int2 wnd = make_int2(wlo[j], whi[j]);
                 const int whi_j = wnd.y < wnd.x ? wnd.x : wnd.y;
                 const double cld = cx - (double)cxf;
                 const float cl = (float)(ASYM ? cld : cld * (double)alo);
-                sm.rec2[slot] = gauss
+                sm.r.rec2[slot] = gauss
                     ? WinRec2<ASYM>::template make<true>(wnd.x, whi_j, i0, ahi, cl)
                     : WinRec2<ASYM>::template make<false>(wnd.x, whi_j, i0, ahi, cl);
             }
@@ -1520,11 +1530,11 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
         // the waves share the two lists
 #pragma unroll 2
         for (int f = wv; f < n_g; f += kWaves)
-            win_record<ASYM, true>(sm.rec[f], sm.rec2[f], u, ul, idx, i0, sig);
+            win_record<ASYM, true>(sm.r.rec[f], sm.r.rec2[f], u, ul, idx, i0, sig);
 #pragma unroll 2
         for (int f = wv; f < n_n; f += kWaves)
-            win_record<ASYM, false>(sm.rec[kCap - 1 - f],
-                                    sm.rec2[kCap - 1 - f], u, ul, idx, i0, sig);
+            win_record<ASYM, false>(sm.r.rec[kCap - 1 - f],
+                                    sm.r.rec2[kCap - 1 - f], u, ul, idx, i0, sig);
         // phases that did not fit (every lane finds the same ranges)
         for (int kl = n_fit + wv; kl < nk; kl += kWaves) {
             const int k = c0 + kl;
@@ -1537,9 +1547,9 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
     }
 
 #pragma unroll
-    for (int p = 0; p < kPPL; ++p) sm.sig[wv][p * kWave + lane] = sig[p];
+    for (int p = 0; p < kPPL; ++p) sm.e.sig[wv][p * kWave + lane] = sig[p];
     __syncthreads();
-    tile_points(P, st, t, s, f_out, sm.sig, sm.rres, sm.red);
+    tile_points(P, st, t, s, f_out, sm.e.sig, sm.e.rres, sm.red);
 }
 
 // ---- peak-major adjoint (windowed mode) -----------------------------------

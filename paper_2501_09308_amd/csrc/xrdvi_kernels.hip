@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kWideWaves * kWave) void k_fused_wide(ProbDev P, St
 // blocks per CU, five with asymmetric records; the sec-law variants are
 // left unbounded).
 template <bool ASYM, bool SEC>
-__global__ __launch_bounds__(kBlock, SEC ? 1 : (ASYM ? 5 : 7)) void k_win(ProbDev P, StepDev st,
+__global__ __launch_bounds__(kBlock, SEC ? 1 : (ASYM ? 6 : 7)) void k_win(ProbDev P, StepDev st,
                                                 float *f_out) {
     __shared__ WinSmem<ASYM> sm;
     // the sec-law variant reads per-sample window and peak records, which

@@ -130,6 +130,33 @@ def test_server_matches_plain_runner_and_graph_matches_direct():
         np.testing.assert_allclose(outs[True][1][k], plain_d[k], rtol=1e-12, atol=1e-12)
 
 
+def test_crowded_tiles_give_the_same_bits_served_and_alone():
+    """More peaks reach each tile than the forward stages in LDS at once
+    (K=256 x 80 peaks on a 40 deg grid: over 1024 peak centres inside a
+    128-point tile), so some phases of each chunk take the global-memory
+    path.  The batched and the single-analysis forwards must split the
+    phases alike: the served result equals its one-at-a-time run bit for
+    bit, symmetric and asymmetric."""
+    ctx = context()
+    prob, y = small_case(905, N=2000, K=256, M=80, cutoff=8.0)
+    per_tile = np.histogram(prob.peak_pos, bins=np.append(
+        prob.x[::128], prob.x[-1]))[0]
+    assert per_tile.max() > 1024
+    S, steps = 4, 4
+    ref = {a: X.xrdvi_plain_run(ctx, prob, y, S, steps, 21 + a, asymmetric=a)
+           for a in (False, True)}
+    srv = X.Server(max_slots=4, steps_per_launch=2, arena_bytes=1 << 29)
+    small, ys = small_case(906, N=1500, K=8, M=12, cutoff=8.0)
+    tk = {a: srv.submit(prob, y, S, steps, 21 + a, asymmetric=a) for a in (False, True)}
+    other = srv.submit(small, ys, 3, 5, 7)
+    res = wait_all(srv, list(tk.values()) + [other])
+    srv.close()
+    for a, t in tk.items():
+        assert res[t][0] == X.XRDVI_OK
+        for k in ("loc", "logscale", "trace"):
+            assert np.array_equal(res[t][2][k], ref[a][k]), (a, k)
+
+
 def test_server_errors_and_cancel():
     prob, y = small_case(600, N=1200, K=6, M=8)
     srv = X.Server(max_slots=1, steps_per_launch=1, arena_bytes=1 << 26)
