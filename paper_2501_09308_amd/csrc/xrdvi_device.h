@@ -36,6 +36,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace xrdvi {
 
 constexpr int kWave = 64;
@@ -1219,73 +1221,61 @@ constexpr int kWinChunk = kBlock;   // phases staged at a time (one per thread)
 // single-analysis and the batched forward: which phases take the
 // global-memory path, and so the order in which a point's terms are summed,
 // depends on it, and a served analysis gives the same bits as its
-// one-at-a-time run only if both kernels stage alike.  24 KB hold 1024
-// symmetric or 768 asymmetric records (six blocks per CU).
+// one-at-a-time run only if both kernels stage alike.  21 KB hold 896
+// symmetric or 672 asymmetric records (seven blocks per CU).
 constexpr int kWinRecBytes = 21 * 1024;
 
-// Second word of a staged record.  The record's FP32 centre relative to the
-// tile is rounded; records whose Gaussian reaches the tile also carry that
-// rounding error cl (x - rho is then formed as (u - centre) + (ul - cl), see
-// PhasePts).  Symmetric peaks: a record without the Gaussian holds its
-// window [lo, hi) as grid indices; a record with it holds the window
-// relative to the tile (both ends clamped to [0, kTile], packed as
-// lo | hi << 16) and cl.  Asymmetric peaks: the window, the scale above the
-// centre and cl.
+// A staged record.  Its FP32 centre relative to the tile is rounded;
+// records whose Gaussian reaches the tile also carry that rounding error cl
+// (x - rho is then formed as (u - centre) + (ul - cl), see PhasePts).
+// Symmetric records keep the centre times the scale below (without the
+// Gaussian) or cl times that scale (with it), so that q2 takes fused
+// multiply-adds (see win_record).  The window is kept relative to the
+// tile: its first point and length, both in [0, kTile], packed as
+// first | length << 16.  One record is read with one address: 24 bytes
+// (symmetric) or 32 (asymmetric: the scale above the centre as well).
 template <bool ASYM>
-struct WinRec2 {
-    int w0, w1;
-    template <bool GAUSS>
-    __device__ __forceinline__ static WinRec2 make(int lo, int hi, int i0,
-                                                   float, float cl) {
-        if (!GAUSS) return WinRec2{lo, hi};
-        const int rl = min(max(lo - i0, 0), kTile), rh = min(max(hi - i0, 0), kTile);
-        return WinRec2{rl | (rh << 16), __float_as_int(cl)};
+struct alignas(8) WinRecord {
+    float c, s, aL, aG;   // centre (or centre times s), 2c/(A w) below, amplitudes
+    int wnd;              // window: first | length << 16
+    float cl;             // the centre's rounding error (times s if symmetric)
+    __device__ __forceinline__ float ahi() const { return s; }
+    __device__ __forceinline__ static WinRecord make(float c, float s, float aL, float aG,
+                                                     int wnd, float, float cl) {
+        return WinRecord{c, s, aL, aG, wnd, cl};
     }
-    // first point and length of the window, in the indices `rel` says
-    template <bool GAUSS>
-    __device__ __forceinline__ int2 window() const {
-        if (!GAUSS) return make_int2(w0, w1 - w0);
-        const int rl = w0 & 0xffff;
-        return make_int2(rl, (w0 >> 16) - rl);
-    }
-    template <bool GAUSS>
-    __device__ __forceinline__ static constexpr bool rel() { return GAUSS; }
-    __device__ __forceinline__ float ahi(float alo) const { return alo; }
-    __device__ __forceinline__ float cl() const { return __int_as_float(w1); }
 };
 template <>
-struct WinRec2<true> {
-    int lo, hi;
-    float ah, cl_;
-    template <bool GAUSS>
-    __device__ __forceinline__ static WinRec2 make(int lo, int hi, int,
-                                                   float ah, float cl) {
-        return WinRec2{lo, hi, ah, cl};
+struct alignas(16) WinRecord<true> {
+    float c, s, aL, aG;
+    int wnd;
+    float cl;
+    float ah;             // 2c/(alpha w): the scale above the centre
+    float pad;
+    __device__ __forceinline__ float ahi() const { return ah; }
+    __device__ __forceinline__ static WinRecord make(float c, float s, float aL, float aG,
+                                                     int wnd, float ah, float cl) {
+        return WinRecord{c, s, aL, aG, wnd, cl, ah, 0.f};
     }
-    template <bool GAUSS>
-    __device__ __forceinline__ int2 window() const {
-        return make_int2(lo, hi - lo);
-    }
-    template <bool GAUSS>
-    __device__ __forceinline__ static constexpr bool rel() { return false; }
-    __device__ __forceinline__ float ahi(float) const { return ah; }
-    __device__ __forceinline__ float cl() const { return cl_; }
 };
+
+// The window [lo, hi) of grid indices relative to the tile starting at i0,
+// clamped to it, as a record holds it.
+__device__ __forceinline__ int win_rel(int lo, int hi, int i0) {
+    const int rl = min(max(lo - i0, 0), kTile), rh = min(max(hi - i0, 0), kTile);
+    return rl | ((rh - rl) << 16);
+}
 
 template <bool ASYM>
 struct WinSmem {
-    static constexpr int kCap = kWinRecBytes / (sizeof(float4) + sizeof(WinRec2<ASYM>));
-    struct Staged {
-        float4 rec[kCap];           // (centre, 2c/(Aw) below, amp L, amp G)
-        WinRec2<ASYM> rec2[kCap];   // window[, 2c/(alpha w)], centre's error
-    };
+    static constexpr int kCap = kWinRecBytes / sizeof(WinRecord<ASYM>);
     struct Sums {
         float sig[kWaves][kTile];   // the waves' partial sums at the points
         float rres[kTile];
     };
     // the last chunk's records are consumed before the sums are written
     union {
-        Staged r;
+        WinRecord<ASYM> rec[kCap];
         Sums e;
     };
     int wmax[kWaves], wmaxn[kWaves], wcnt[kWaves], wcntg[kWaves];
@@ -1330,42 +1320,47 @@ __device__ void win_phase_global(const SegPeaks &sp, int4 r, int2 r2,
         sig[p] = fmaf(aL, accL[p], fmaf(aG, accG[p], sig[p]));
 }
 
-// One staged record's terms at the lane's points (a: centre, scale below,
-// Lorentzian and Gaussian amplitudes; b: window, the scale above and, with
-// the Gaussian, the centre's rounding error).  Symmetric records hold the
-// centre times the scale in place of the centre when they have no Gaussian,
-// and the centre's rounding error times the scale when they have one, so
-// that q2 takes fused multiply-adds.
+// One staged record's terms at the lane's points (lane and lane + 64 of
+// the tile).  Only the lanes whose point lies in the window take part: a
+// half tile the window misses is skipped by the whole wave.
 template <bool ASYM, bool GAUSS>
-__device__ __forceinline__ void win_record(const float4 a, const WinRec2<ASYM> b,
+__device__ __forceinline__ void win_record(const WinRecord<ASYM> r,
                                            const float (&u)[kPPL],
-                                           const float (&ul)[kPPL],
-                                           const int (&idx)[kPPL], int i0,
+                                           const float (&ul)[kPPL], int lane,
                                            float (&sig)[kPPL]) {
-    const float ah = b.ahi(a.y);
-    const int2 wnd = b.template window<GAUSS>();
-    const float cl = GAUSS ? b.cl() : 0.f;
+    const float ah = r.ahi();
+    const int d0 = lane - (r.wnd & 0xffff), len = r.wnd >> 16;
 #pragma unroll
     for (int p = 0; p < kPPL; ++p) {
-        // only the lanes whose point lies in the window take part: a half
-        // tile the window misses is skipped by the whole wave
-        const int ii = WinRec2<ASYM>::template rel<GAUSS>() ? idx[p] - i0 : idx[p];
-        if ((unsigned)(ii - wnd.x) < (unsigned)wnd.y) {
+        const bool in = (unsigned)(d0 + p * kWave) < (unsigned)len;
+        if (GAUSS) {
+            if (in) {
+                float q2;
+                if (ASYM) {
+                    const float d = (u[p] - r.c) + (ul[p] - r.cl);
+                    q2 = d * (d >= 0.f ? ah : r.s);
+                } else {
+                    // (u - centre) s + (ul s - cl s), cl s kept in the record
+                    q2 = fmaf(u[p] - r.c, r.s, fmaf(ul[p], r.s, -r.cl));
+                }
+                const float tt = fmaf(q2, q2, 1.0f);
+                sig[p] = fmaf(r.aL, rcp_f32(tt), sig[p]);
+                sig[p] = fmaf(r.aG, exp2_f32(-tt), sig[p]);
+            }
+        } else if (in) {
+            // (an empty volatile statement keeps this short body a branch,
+            // which the wave skips when the half misses the window; the
+            // compiler would otherwise evaluate it at both halves and select)
+            asm volatile("");
             float q2;
             if (ASYM) {
-                float d = u[p] - a.x;
-                if (GAUSS) d += ul[p] - cl;
-                q2 = d * (d >= 0.f ? ah : a.y);
-            } else if (GAUSS) {
-                // (u - centre) s + (ul s - cl s), cl s kept in the record
-                q2 = fmaf(u[p] - a.x, a.y, fmaf(ul[p], a.y, -cl));
+                const float d = u[p] - r.c;
+                q2 = d * (d >= 0.f ? ah : r.s);
             } else {
                 // u s - centre s, centre s kept in the record (far peaks)
-                q2 = fmaf(u[p], a.y, -a.x);
+                q2 = fmaf(u[p], r.s, -r.c);
             }
-            const float tt = fmaf(q2, q2, 1.0f);
-            sig[p] = fmaf(a.z, rcp_f32(tt), sig[p]);
-            if (GAUSS) sig[p] = fmaf(a.w, exp2_f32(-tt), sig[p]);
+            sig[p] = fmaf(r.aL, rcp_f32(fmaf(q2, q2, 1.0f)), sig[p]);
         }
     }
 }
@@ -1496,15 +1491,13 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
                 // without the Gaussian) or the rounding error of the centre
                 // times the scale (with it), so that q2 takes fused
                 // multiply-adds (see win_record)
-                sm.r.rec[slot] = make_float4(ASYM || gauss ? cxf : (float)(cx * (double)alo),
-                                           alo, I * aL, gauss ? I * aG : 0.f);
                 const int2 wnd = make_int2(wlo[j], whi[j]);
                 const int whi_j = wnd.y < wnd.x ? wnd.x : wnd.y;
                 const double cld = cx - (double)cxf;
                 const float cl = (float)(ASYM ? cld : cld * (double)alo);
-                sm.r.rec2[slot] = gauss
-                    ? WinRec2<ASYM>::template make<true>(wnd.x, whi_j, i0, ahi, cl)
-                    : WinRec2<ASYM>::template make<false>(wnd.x, whi_j, i0, ahi, cl);
+                sm.rec[slot] = WinRecord<ASYM>::make(
+                    ASYM || gauss ? cxf : (float)(cx * (double)alo), alo, I * aL,
+                    gauss ? I * aG : 0.f, win_rel(wnd.x, whi_j, i0), ahi, gauss ? cl : 0.f);
             }
         }
         // staged record counts and number of fitting phases
@@ -1530,11 +1523,9 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
         // the waves share the two lists
 #pragma unroll 2
         for (int f = wv; f < n_g; f += kWaves)
-            win_record<ASYM, true>(sm.r.rec[f], sm.r.rec2[f], u, ul, idx, i0, sig);
-#pragma unroll 2
-        for (int f = wv; f < n_n; f += kWaves)
-            win_record<ASYM, false>(sm.r.rec[kCap - 1 - f],
-                                    sm.r.rec2[kCap - 1 - f], u, ul, idx, i0, sig);
+            win_record<ASYM, true>(sm.rec[f], u, ul, lane, sig);
+        for (int f = wv; f < n_n; f += kWaves)   // (its body keeps a branch: not unrolled)
+            win_record<ASYM, false>(sm.rec[kCap - 1 - f], u, ul, lane, sig);
         // phases that did not fit (every lane finds the same ranges)
         for (int kl = n_fit + wv; kl < nk; kl += kWaves) {
             const int k = c0 + kl;
@@ -1672,6 +1663,7 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
     const float ka = ASYM ? (float)ph[4 * K + k] : 1.f;
     const bool unif = P.uniform != 0;
     const double xl = fma((double)lane, P.dx, P.x0);   // uniform grid: x0 + lane dx
+    const double dxw = kWave * P.dx;                     // one chunk of points
     const int a = P.off[k], b = P.off[k + 1];
     float acc[NS];
 #pragma unroll
@@ -1704,54 +1696,68 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
         // each peak's residuals through a buffer view that ends with its
         // window: lanes past the window read 0 and so weigh their point by 0
         __amdgpu_buffer_rsrc_t rq[kAdjPeaks];
+        // x_i - rho = e + t in FP64.  On a uniform grid x_i is formed, not
+        // loaded, so only the residuals are read: e is the lane's offset in
+        // the first chunk, x0 + (lo + lane) dx - rho, and t the chunk's c dx;
+        // otherwise e = -rho and t = x_i, loaded
+        double e[kAdjPeaks];
 #pragma unroll
-        for (int q = 0; q < kAdjPeaks; ++q)
+        for (int q = 0; q < kAdjPeaks; ++q) {
             rq[q] = __builtin_amdgcn_make_buffer_rsrc(
                 (void *)(rres_s + lo[q]), (short)0, len[q] * 4, kBufferFlags);
-        for (int c = 0; c < span; c += kWave) {
-            float R[kAdjPeaks], rv[kAdjPeaks], d[kAdjPeaks];
-            double xv[kAdjPeaks];
-#pragma unroll
-            for (int q = 0; q < kAdjPeaks; ++q) {
-                // every lane loads; points past the grid's end (a window
-                // ending at N, or lo = N for an empty one) read 0 from the
-                // bounded grid view, and their residual is 0
-                const int ii = lo[q] + c + lane;
-                rv[q] = __uint_as_float(
-                    __builtin_amdgcn_raw_buffer_load_b32(rq[q], (c + lane) * 4, 0, 0));
-                // a uniform grid's x_i = x0 + i dx is formed in FP64, not
-                // loaded, so only the residuals are read
-                xv[q] = unif ? fma((double)(lo[q] + c), P.dx, xl)
-                             : __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                                              x_rs, ii * 8, 0, 0));
-            }
-            // all loads are issued before the first use, so one memory
-            // latency covers them
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int q = 0; q < kAdjPeaks; ++q) {
-                R[q] = rv[q] * I[q];
-                d[q] = (float)(xv[q] - rho[q]);
-            }
-            AdjPt pt[kAdjPeaks];
-            SecW wl[kAdjPeaks], wh[kAdjPeaks];
-            bool gauss = false;
-#pragma unroll
-            for (int q = 0; q < kAdjPeaks; ++q) {
-                wl[q] = SecW::of(SEC ? tw[q] : 0.f);
-                wh[q] = SecW::of(SEC ? tw[q] * ka : 0.f);
-                pt[q] = adj_point_L<ASYM, SEC>(R[q], d[q], iw2 * cq[q], iw2r * cq[q],
-                                               cq[q], wl[q], wh[q], acc);
-                // (points outside the window lie beyond 8 FWHM: no effect)
-                gauss = gauss | (pt[q].tt <= kGaussTT);
-            }
-            // one wave-uniform branch over the four peaks' Gaussian terms
-            if (__builtin_amdgcn_readfirstlane(__any(gauss))) {
-#pragma unroll
-                for (int q = 0; q < kAdjPeaks; ++q)
-                    adj_point_G<ASYM, SEC>(pt[q], cq[q], wl[q], wh[q], acc);
-            }
+            e[q] = unif ? fma((double)lo[q], P.dx, xl) - rho[q] : -rho[q];
         }
+        // the chunks of the peaks' windows, one loop per kind of grid
+        auto chunks = [&](auto unif_tag) {
+            constexpr bool UNIF = decltype(unif_tag)::value;
+            double cdx = 0.0;
+            for (int c = 0; c < span; c += kWave, cdx += dxw) {
+                float R[kAdjPeaks], rv[kAdjPeaks], d[kAdjPeaks];
+                double xv[kAdjPeaks];
+#pragma unroll
+                for (int q = 0; q < kAdjPeaks; ++q) {
+                    // every lane loads; points past the grid's end (a window
+                    // ending at N, or lo = N for an empty one) read 0 from
+                    // the bounded grid view, and their residual is 0
+                    rv[q] = __uint_as_float(
+                        __builtin_amdgcn_raw_buffer_load_b32(rq[q], (c + lane) * 4, 0, 0));
+                    if (!UNIF)
+                        xv[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                               x_rs, (lo[q] + c + lane) * 8, 0, 0));
+                }
+                // all loads are issued before the first use, so one memory
+                // latency covers them
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = 0; q < kAdjPeaks; ++q) {
+                    R[q] = rv[q] * I[q];
+                    d[q] = (float)(e[q] + (UNIF ? cdx : xv[q]));
+                }
+                AdjPt pt[kAdjPeaks];
+                SecW wl[kAdjPeaks], wh[kAdjPeaks];
+                bool gauss = false;
+#pragma unroll
+                for (int q = 0; q < kAdjPeaks; ++q) {
+                    wl[q] = SecW::of(SEC ? tw[q] : 0.f);
+                    wh[q] = SecW::of(SEC ? tw[q] * ka : 0.f);
+                    pt[q] = adj_point_L<ASYM, SEC>(R[q], d[q], iw2 * cq[q], iw2r * cq[q],
+                                                   cq[q], wl[q], wh[q], acc);
+                    // (points outside the window lie beyond 8 FWHM: no effect)
+                    gauss = gauss | (pt[q].tt <= kGaussTT);
+                }
+                // one wave-uniform branch over the four peaks' Gaussian terms
+                // (a ballot is a scalar value: no lane-to-scalar move)
+                if (__builtin_amdgcn_ballot_w64(gauss) != 0) {
+#pragma unroll
+                    for (int q = 0; q < kAdjPeaks; ++q)
+                        adj_point_G<ASYM, SEC>(pt[q], cq[q], wl[q], wh[q], acc);
+                }
+            }
+        };
+        if (unif)
+            chunks(std::true_type{});
+        else
+            chunks(std::false_type{});
     }
 #pragma unroll
     for (int c = 0; c < NS; ++c) acc[c] = wave_total_f32(acc[c]);
