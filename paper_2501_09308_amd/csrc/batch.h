@@ -74,9 +74,16 @@ inline void batch_units(const ProbDev &P, int S, int units[kKinds]) {
     units[kGrad] = P.K;
 }
 
-// One batched step.  sec: also launch the sec-law variants (needed only
-// while some resident analysis uses that width law).
+// Variant class of an analysis (0..7): windowed (bit 0), asymmetric peaks
+// (bit 1), sec-law width (bit 2).  Each class has its own fused and adjoint
+// kernels; a batched step launches only those of the resident classes.
+inline int batch_class(const ProbDev &P) {
+    return (P.cutoff > 0.0 ? 1 : 0) | (P.D == 5 ? 2 : 0) | (P.sec != 0 ? 4 : 0);
+}
+
+// One batched step over the resident analyses, whose classes are the set
+// bits of `classes` (bit c: some resident analysis has class c).
 hipError_t launch_batch_step(const SlotDev *tab, const SchedDev *sch,
-                             hipStream_t stream, bool sec);
+                             hipStream_t stream, unsigned classes);
 
 }  // namespace xrdvi

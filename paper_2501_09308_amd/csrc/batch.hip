@@ -244,30 +244,39 @@ __global__ void kb_advance(const SlotDev *tab, const SchedDev *sch) {
 }
 
 hipError_t launch_batch_step(const SlotDev *tab, const SchedDev *sch,
-                             hipStream_t s, bool sec) {
+                             hipStream_t s, unsigned classes) {
+    // whether a resident class satisfies the windowed / sec-law test
+    const auto any = [classes](int want_win, int want_sec) {
+        for (int c = 0; c < 8; ++c)
+            if ((classes >> c & 1u) && (want_win < 0 || (c & 1) == want_win) &&
+                (want_sec < 0 || (c >> 2 & 1) == want_sec))
+                return true;
+        return false;
+    };
+    const auto has = [classes](bool win, bool asym, bool sec) {
+        return (classes >> ((win ? 1 : 0) | (asym ? 2 : 0) | (sec ? 4 : 0)) & 1u) != 0;
+    };
     kb_sample<<<kGridSmall, 256, 0, s>>>(tab, sch);
-    kb_windows<false><<<kGridLarge, 256, 0, s>>>(tab, sch);
-    if (sec) kb_windows<true><<<kGridLarge, 256, 0, s>>>(tab, sch);
-    kb_plan<false><<<kGridLarge, 256, 0, s>>>(tab, sch);
-    if (sec) kb_plan<true><<<kGridLarge, 256, 0, s>>>(tab, sch);
-    kb_cand_ext<<<kGridSmall, kCandThreads, 0, s>>>(tab, sch);
-    kb_cand<<<kGridLarge, kCandThreads, 0, s>>>(tab, sch);
-    kb_fused<true, false, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-    kb_fused<false, false, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-    kb_fused<true, true, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-    kb_fused<false, true, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-    if (sec) {
-        kb_fused<true, false, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-        kb_fused<false, false, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-        kb_fused<true, true, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-        kb_fused<false, true, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    if (any(1, 0)) kb_windows<false><<<kGridLarge, 256, 0, s>>>(tab, sch);
+    if (any(-1, 1)) kb_windows<true><<<kGridLarge, 256, 0, s>>>(tab, sch);
+    if (any(0, 0)) kb_plan<false><<<kGridLarge, 256, 0, s>>>(tab, sch);
+    if (any(0, 1)) kb_plan<true><<<kGridLarge, 256, 0, s>>>(tab, sch);
+    if (any(1, 0)) {
+        kb_cand_ext<<<kGridSmall, kCandThreads, 0, s>>>(tab, sch);
+        kb_cand<<<kGridLarge, kCandThreads, 0, s>>>(tab, sch);
     }
-    kb_adjoint<false, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-    kb_adjoint<true, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-    if (sec) {
-        kb_adjoint<false, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-        kb_adjoint<true, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
-    }
+    if (has(true, false, false)) kb_fused<true, false, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    if (has(false, false, false)) kb_fused<false, false, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    if (has(true, true, false)) kb_fused<true, true, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    if (has(false, true, false)) kb_fused<false, true, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    if (has(true, false, true)) kb_fused<true, false, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    if (has(false, false, true)) kb_fused<false, false, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    if (has(true, true, true)) kb_fused<true, true, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    if (has(false, true, true)) kb_fused<false, true, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    if (has(true, false, false)) kb_adjoint<false, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    if (has(true, true, false)) kb_adjoint<true, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    if (has(true, false, true)) kb_adjoint<false, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
+    if (has(true, true, true)) kb_adjoint<true, true><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
     kb_elbo<<<kGridElbo, 1024, 0, s>>>(tab, sch);
     kb_grad_adam<<<kGridLarge, 256, 0, s>>>(tab, sch);
     kb_advance<<<1, 1024, 0, s>>>(tab, sch);

@@ -90,7 +90,7 @@ class GpuExecutor : public Executor {
     ~GpuExecutor() override {
         (void)hipSetDevice(device_);
         (void)hipStreamSynchronize(stream_);
-        for (int v = 0; v < 2; ++v) {
+        for (int v = 0; v < kClassSets; ++v) {
             if (gexec_[v]) (void)hipGraphExecDestroy(gexec_[v]);
             if (graph_[v]) (void)hipGraphDestroy(graph_[v]);
         }
@@ -152,9 +152,9 @@ class GpuExecutor : public Executor {
         std::vector<std::pair<int, uint64_t>> members;
         for (const Job *j : active) members.emplace_back(j->slot, j->ticket);
         std::sort(members.begin(), members.end());
-        // the sec-law kernels run only while such an analysis is resident
-        bool sec = false;
-        for (const auto &m : members) sec = sec || h_tab_[m.first].P.sec != 0;
+        // each variant's kernels run only while an analysis of it is resident
+        unsigned classes = 0;
+        for (const auto &m : members) classes |= 1u << batch_class(h_tab_[m.first].P);
         hipError_t e = hipSuccess;
         if (changed || members != members_) {
             members_ = members;
@@ -174,12 +174,12 @@ class GpuExecutor : public Executor {
         }
         if (e == hipSuccess) {
             if (use_graph_) {
-                if (!gexec_[sec]) e = capture(sec);
+                if (!gexec_[classes]) e = capture(classes);
                 for (int done = 0; e == hipSuccess && done < steps; done += graph_steps_)
-                    e = hipGraphLaunch(gexec_[sec], stream_);
+                    e = hipGraphLaunch(gexec_[classes], stream_);
             } else {
                 for (int i = 0; e == hipSuccess && i < steps; ++i)
-                    e = launch_batch_step(d_tab_, d_sch_, stream_, sec);
+                    e = launch_batch_step(d_tab_, d_sch_, stream_, classes);
             }
         }
         if (e == hipSuccess)
@@ -222,12 +222,12 @@ class GpuExecutor : public Executor {
     }
 
     // One graph holding graph_steps_ batched steps; kernels read the slot
-    // table and work prefix from fixed device buffers.  Two variants: with
-    // and without the sec-law kernels.
-    hipError_t capture(bool sec) {
+    // table and work prefix from fixed device buffers.  One graph per set of
+    // resident variant classes, captured when that set first occurs.
+    hipError_t capture(unsigned classes) {
         hipError_t e = hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal);
         for (int i = 0; e == hipSuccess && i < graph_steps_; ++i)
-            e = launch_batch_step(d_tab_, d_sch_, stream_, sec);
+            e = launch_batch_step(d_tab_, d_sch_, stream_, classes);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(stream_, &g);
         if (e == hipSuccess) e = e2;
@@ -235,8 +235,8 @@ class GpuExecutor : public Executor {
             if (g) (void)hipGraphDestroy(g);
             return e;
         }
-        graph_[sec] = g;
-        return hipGraphInstantiate(&gexec_[sec], graph_[sec], nullptr, nullptr, 0);
+        graph_[classes] = g;
+        return hipGraphInstantiate(&gexec_[classes], graph_[classes], nullptr, nullptr, 0);
     }
 
     int device_;
@@ -251,8 +251,9 @@ class GpuExecutor : public Executor {
     int *d_steps_ = nullptr;
     int h_steps_[kMaxSlots] = {};
     std::vector<std::pair<int, uint64_t>> members_;
-    hipGraph_t graph_[2] = {nullptr, nullptr};
-    hipGraphExec_t gexec_[2] = {nullptr, nullptr};
+    static constexpr int kClassSets = 256;   // subsets of the 8 variant classes
+    hipGraph_t graph_[kClassSets] = {};
+    hipGraphExec_t gexec_[kClassSets] = {};
 };
 
 // Validates a request and builds the job (host copies, default init).

@@ -157,6 +157,36 @@ def test_crowded_tiles_give_the_same_bits_served_and_alone():
             assert np.array_equal(res[t][2][k], ref[a][k]), (a, k)
 
 
+def test_every_variant_class_comes_and_goes():
+    """Analyses of all eight variants (dense or windowed, symmetric or
+    asymmetric peaks, constant or sec-law width), with different step
+    counts, pass through a three-slot server, so that the set of resident
+    variants, and with it the launched kernels and the replayed graph,
+    changes many times.  Each result equals its one-at-a-time run bit for
+    bit."""
+    ctx = context()
+    prob, y = small_case(910, N=1400, K=6, M=10, cutoff=8.0)
+    S = 3
+    cases = []
+    for i, (cut, asym, law) in enumerate(
+            [(c, a, w) for w in (0, "sec") for a in (False, True)
+             for c in (0.0, 8.0)]):
+        p = W.Problem(x=prob.x, bg=prob.bg, peak_off=prob.peak_off,
+                      peak_pos=prob.peak_pos, peak_int=prob.peak_int, cutoff=cut,
+                      true_idx=prob.true_idx, phi_true=prob.phi_true)
+        cases.append((p, dict(asymmetric=asym, width_law=law), 3 + 2 * i, 60 + i))
+    refs = [X.xrdvi_plain_run(ctx, p, y, S, steps, seed, **kw)
+            for p, kw, steps, seed in cases]
+    srv = X.Server(max_slots=3, steps_per_launch=2, arena_bytes=1 << 28)
+    tickets = [srv.submit(p, y, S, steps, seed, **kw) for p, kw, steps, seed in cases]
+    res = wait_all(srv, tickets)
+    srv.close()
+    for t, ref, (_, kw, _, _) in zip(tickets, refs, cases):
+        assert res[t][0] == X.XRDVI_OK
+        for k in ("loc", "logscale", "trace"):
+            assert np.array_equal(res[t][2][k], ref[k]), (kw, k)
+
+
 def test_server_errors_and_cancel():
     prob, y = small_case(600, N=1200, K=6, M=8)
     srv = X.Server(max_slots=1, steps_per_launch=1, arena_bytes=1 << 26)
