@@ -1380,6 +1380,17 @@ __device__ __forceinline__ int2 xcd_tile_sample(int ntiles, int S) {
     return make_int2(q / S, q % S);
 }
 
+// Block order of the windowed forward when S is a multiple of 8: XCD x
+// takes samples [x S/8, (x+1) S/8) of every tile, tile by tile.  Its L2 then
+// holds the window arrays of its own samples (each staged record reads its
+// window's ends from them, one cache line per phase), which tile-major runs
+// over all samples overflow when the phases are many.
+__device__ __forceinline__ int2 xcd_sample_group(int S) {
+    const int b = blockIdx.x + blockIdx.y * gridDim.x;
+    const int G = S / kXcds, i = b / kXcds;
+    return make_int2(i / G, (b % kXcds) * G + i % G);
+}
+
 template <bool ASYM, bool SEC, typename SM>
 __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
                          float *f_out, SM &sm) {

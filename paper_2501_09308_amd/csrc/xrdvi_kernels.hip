@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kWideWaves * kWave) void k_fused_wide(ProbDev P, St
 // a3 + a4 (windowed): forward tile over its staged peak records; grid
 // (ntiles, S), kBlock threads, blocks ordered by XCD (constant width).  The
 // register budget is held to the occupancy the staging space allows (seven
-// blocks per CU, five with asymmetric records; the sec-law variants are
+// blocks per CU, six with asymmetric records; the sec-law variants are
 // left unbounded).
 template <bool ASYM, bool SEC>
 __global__ __launch_bounds__(kBlock, SEC ? 1 : (ASYM ? 6 : 7)) void k_win(ProbDev P, StepDev st,
@@ -133,7 +133,8 @@ __global__ __launch_bounds__(kBlock, SEC ? 1 : (ASYM ? 6 : 7)) void k_win(ProbDe
     // the sec-law variant reads per-sample window and peak records, which
     // the default order (tile fastest) keeps to a few samples per L2
     const int2 ts = SEC ? make_int2(blockIdx.x, blockIdx.y)
-                        : xcd_tile_sample(P.ntiles, st.S);
+                  : st.S % kXcds == 0 ? xcd_sample_group(st.S)
+                                      : xcd_tile_sample(P.ntiles, st.S);
     win_tile<ASYM, SEC>(P, st, ts.x, ts.y, f_out, sm);
 }
 
