@@ -164,7 +164,16 @@ __global__ __launch_bounds__(kBlock) void kb_fused(const SlotDev *tab,
         const SlotDev &d = slot_entry(tab, ps, i);
         if (!running(d)) continue;
         const int local = local_unit(ps, i, u);
-        const int t = local % d.P.ntiles, s = local / d.P.ntiles;
+        int t = local % d.P.ntiles, s = local / d.P.ntiles;
+        if (WIN && !SEC && d.st.S % kXcds == 0) {
+            // a block runs on XCD u mod 8, and u - local is the same for all
+            // of an analysis's units: the units with one value of local mod 8
+            // share an XCD, which takes one eighth of the samples of every
+            // tile (its L2 keeps those samples' window arrays)
+            const int G = d.st.S / kXcds, q = local / kXcds;
+            t = q / G;
+            s = (local % kXcds) * G + q % G;
+        }
         if (s >= d.st.S) continue;
         // windowed: forward only (the adjoint is peak-major); dense: fused
         if constexpr (WIN) {
