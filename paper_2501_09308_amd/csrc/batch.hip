@@ -151,7 +151,8 @@ __global__ __launch_bounds__(kCandThreads) void kb_cand(const SlotDev *tab,
 }
 
 // The windowed constant-width variants are held to the six blocks per CU
-// their LDS allows (80 VGPRs, a few spilled once per unit): their waves wait
+// their LDS allows (80 VGPRs; six 8-byte values are spilled once per block
+// and reloaded once per unit, outside the record loops): their waves wait
 // on memory more than their single-analysis counterpart's.
 template <bool WIN, bool ASYM, bool SEC>
 __global__ __launch_bounds__(kBlock, WIN && !SEC ? 6 : 1) void kb_fused(const SlotDev *tab,
