@@ -71,7 +71,7 @@ inline void batch_units(const ProbDev &P, int S, int units[kKinds]) {
     units[fused_kind(win, asym, sec)] = P.ntiles * S;
     if (win) units[adjoint_kind(asym, sec)] = P.K * S;
     units[kElbo] = 1;
-    units[kGrad] = P.K;
+    units[kGrad] = win ? (P.K + kWaves - 1) / kWaves : P.K;   // windowed: a phase per wave
 }
 
 // Variant class of an analysis (0..7): windowed (bit 0), asymmetric peaks

@@ -233,15 +233,23 @@ __global__ __launch_bounds__(256) void kb_grad_adam(const SlotDev *tab,
         const int i = find_slot(ps, u);
         const SlotDev &d = slot_entry(tab, ps, i);
         if (!running(d)) continue;
-        const int k = local_unit(ps, i, u);
-        if (k >= d.P.K) continue;
         AdamArgs a;
         a.m1_loc = d.m1_loc; a.m2_loc = d.m2_loc;
         a.m1_ls = d.m1_ls; a.m2_ls = d.m2_ls;
         a.t = *d.step + 1;
         a.lr = d.lr; a.b1 = 0.9; a.b2 = 0.999; a.eps = 1e-8;
-        grad_block(d.P, d.st, k, 1.0, nullptr, nullptr, nullptr,
-                   d.loc, d.logscale, &a, sm);
+        if (d.P.cutoff > 0.0) {
+            // windowed: one phase per wave
+            const int k = local_unit(ps, i, u) * kWaves + (int)(threadIdx.x / kWave);
+            if (k < d.P.K)
+                grad_wave(d.P, d.st, k, 1.0, nullptr, nullptr, nullptr, d.loc,
+                          d.logscale, &a);
+        } else {
+            const int k = local_unit(ps, i, u);
+            if (k >= d.P.K) continue;
+            grad_block(d.P, d.st, k, 1.0, nullptr, nullptr, nullptr,
+                       d.loc, d.logscale, &a, sm);
+        }
         __syncthreads();
     }
 }

@@ -169,6 +169,19 @@ __global__ __launch_bounds__(256) void k_grad(ProbDev P, StepDev st,
                nullptr, nullptr, sm, gz_out);
 }
 
+// a7, windowed: one wave per phase, grid ceil(K / 4).
+__global__ __launch_bounds__(256) void k_grad_win(ProbDev P, StepDev st,
+                                                  double scale,
+                                                  const double *scale_dev,
+                                                  double *gloc,
+                                                  double *glogscale,
+                                                  double *gz_out) {
+    const int k = blockIdx.x * kWaves + (int)(threadIdx.x / kWave);
+    if (k < P.K)
+        grad_wave(P, st, k, scale, scale_dev, gloc, glogscale, nullptr, nullptr,
+                  nullptr, gz_out);
+}
+
 // a8: Adam ascent step on n coordinates.
 __global__ void k_adam(int n, double *theta, double *m1, double *m2,
                        const double *__restrict__ g, int t, double lr,
@@ -304,8 +317,12 @@ hipError_t launch_grad(const ProbDev &P, const StepDev &st, double scale,
                        const double *scale_dev, double *gloc,
                        double *glogscale, hipStream_t stream,
                        double *gz_out) {
-    k_grad<<<P.K, 256, 0, stream>>>(P, st, scale, scale_dev, gloc, glogscale,
-                                    gz_out);
+    if (P.cutoff > 0.0)
+        k_grad_win<<<(P.K + kWaves - 1) / kWaves, 256, 0, stream>>>(
+            P, st, scale, scale_dev, gloc, glogscale, gz_out);
+    else
+        k_grad<<<P.K, 256, 0, stream>>>(P, st, scale, scale_dev, gloc, glogscale,
+                                        gz_out);
     return hipGetLastError();
 }
 

@@ -254,6 +254,72 @@ __device__ inline void phase_grad(const ProbDev &P, const double *E, double h,
     }
 }
 
+// The part of phase k's gradient from sample s with adjoint sums E: the
+// chain rule through the transforms, the prior and the Jacobian, added to
+// this lane's sums am (for loc) and as (for logscale).
+__device__ inline void grad_sample(const ProbDev &P, const StepDev &st, int k, int s,
+                                   const double (&E)[12], double (&am)[5],
+                                   double (&as)[5], double *gz_out) {
+#pragma clang fp contract(off)
+    const int K = P.K, D = P.D * K, NT = P.D;
+    const double *ph = st.phi + (size_t)s * D;
+    const double h = ph[k], mu = ph[K + k], w = ph[2 * K + k], r = ph[3 * K + k];
+    const double al = P.D == 5 ? ph[4 * K + k] : 1.0;
+    double gp[5];
+    phase_grad(P, E, h, w, r, al, gp);
+    double gz[5];
+    gz[0] = h * gp[0] - P.lambda * h + 1.0;
+    gz[1] = gp[1] - mu / (P.mu_sd * P.mu_sd);
+    gz[2] = w * gp[2] + (P.w_shape - 1.0) - P.w_rate * w + 1.0;
+    gz[3] = r * (1.0 - r) * gp[3] + 1.0 - 2.0 * r;
+    gz[4] = P.D == 5
+        ? al * gp[4] - al * (al - P.a_mean) / (P.a_sd * P.a_sd) + 1.0
+        : 0.0;
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+        if (t >= NT) break;
+        const int j = t * K + k;
+        if (gz_out) gz_out[(size_t)s * D + j] = gz[t];
+        am[t] += gz[t];
+        as[t] += gz[t] * st.eps[(size_t)s * D + j] * st.sd[j];
+    }
+}
+
+// One wave: sums am and as over its lanes; lane 0 stores the gradient of
+// phase k's 2 D parameters, or with `adam` updates loc / logscale in place.
+__device__ inline void grad_finish(const ProbDev &P, const StepDev &st, int k,
+                                   double scale, const double *scale_dev,
+                                   double *gloc, double *glogscale, double *loc,
+                                   double *logscale, const AdamArgs *adam,
+                                   double (&am)[5], double (&as)[5]) {
+#pragma clang fp contract(off)
+    const int K = P.K, S = st.S, NT = P.D;
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+        am[t] = wave_sum(am[t]);
+        as[t] = wave_sum(as[t]);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        if (scale_dev) scale *= *scale_dev;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            if (t >= NT) break;
+            const int j = t * K + k;
+            const double gl = scale * (am[t] / S);
+            const double gs = scale * (as[t] / S + 1.0);
+            if (adam) {
+                adam_update(loc[j], adam->m1_loc[j], adam->m2_loc[j], gl,
+                            adam->t, adam->lr, adam->b1, adam->b2, adam->eps);
+                adam_update(logscale[j], adam->m1_ls[j], adam->m2_ls[j], gs,
+                            adam->t, adam->lr, adam->b1, adam->b2, adam->eps);
+            } else if (gloc) {
+                gloc[j] = gl;
+                glogscale[j] = gs;
+            }
+        }
+    }
+}
+
 __device__ inline void grad_block(const ProbDev &P, const StepDev &st, int k,
                                   double scale, const double *scale_dev,
                                   double *gloc, double *glogscale,
@@ -261,7 +327,7 @@ __device__ inline void grad_block(const ProbDev &P, const StepDev &st, int k,
                                   const AdamArgs *adam, GradSmem &sm,
                                   double *gz_out = nullptr) {
 #pragma clang fp contract(off)
-    const int K = P.K, D = P.D * K, S = st.S, NT = P.D;
+    const int K = P.K, S = st.S;
     const int NS = num_sums(P.D);
     const int SG = S < kWave ? S : kWave;
     const int G = 256 / SG;
@@ -297,57 +363,41 @@ __device__ inline void grad_block(const ProbDev &P, const StepDev &st, int k,
             for (int gg = 0; gg < G; ++gg)
 #pragma unroll
                 for (int c = 0; c < 12; ++c) E[c] += sm.red[gg * SG + sl][c];
-            const double *ph = st.phi + (size_t)s * D;
-            const double h = ph[k], mu = ph[K + k], w = ph[2 * K + k],
-                         r = ph[3 * K + k];
-            const double al = P.D == 5 ? ph[4 * K + k] : 1.0;
-            double gp[5];
-            phase_grad(P, E, h, w, r, al, gp);
-            double gz[5];
-            gz[0] = h * gp[0] - P.lambda * h + 1.0;
-            gz[1] = gp[1] - mu / (P.mu_sd * P.mu_sd);
-            gz[2] = w * gp[2] + (P.w_shape - 1.0) - P.w_rate * w + 1.0;
-            gz[3] = r * (1.0 - r) * gp[3] + 1.0 - 2.0 * r;
-            gz[4] = P.D == 5
-                ? al * gp[4] - al * (al - P.a_mean) / (P.a_sd * P.a_sd) + 1.0
-                : 0.0;
-#pragma unroll
-            for (int t = 0; t < 5; ++t) {
-                if (t >= NT) break;
-                const int j = t * K + k;
-                if (gz_out) gz_out[(size_t)s * D + j] = gz[t];
-                am[t] += gz[t];
-                as[t] += gz[t] * st.eps[(size_t)s * D + j] * st.sd[j];
-            }
+            grad_sample(P, st, k, s, E, am, as, gz_out);
         }
         __syncthreads();
     }
-    if (tid < kWave) {
+    if (tid < kWave)
+        grad_finish(P, st, k, scale, scale_dev, gloc, glogscale, loc, logscale, adam,
+                    am, as);
+}
+
+// The gradient of phase k of a windowed analysis by one wave: its adjoint
+// sums are already per (phase, sample), so the lanes take the samples (64
+// per pass) and no block-wide reduction is needed.  The same arithmetic, in
+// the same order, as grad_block.
+__device__ inline void grad_wave(const ProbDev &P, const StepDev &st, int k,
+                                 double scale, const double *scale_dev,
+                                 double *gloc, double *glogscale, double *loc,
+                                 double *logscale, const AdamArgs *adam,
+                                 double *gz_out = nullptr) {
+#pragma clang fp contract(off)
+    const int S = st.S, NS = num_sums(P.D);
+    const int lane = threadIdx.x & (kWave - 1);
+    double am[5] = {0, 0, 0, 0, 0}, as[5] = {0, 0, 0, 0, 0};
+    for (int s0 = 0; s0 < S; s0 += kWave) {
+        const int s = s0 + lane;
+        if (s < S) {
+            // (0 + sum, as grad_block's combination of its groups forms it)
+            double E[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+            const double *src = st.pw + ((size_t)k * S + s) * NS;
 #pragma unroll
-        for (int t = 0; t < 5; ++t) {
-            am[t] = wave_sum(am[t]);
-            as[t] = wave_sum(as[t]);
-        }
-        if (tid == 0) {
-            if (scale_dev) scale *= *scale_dev;
-#pragma unroll
-            for (int t = 0; t < 5; ++t) {
-                if (t >= NT) break;
-                const int j = t * K + k;
-                const double gl = scale * (am[t] / S);
-                const double gs = scale * (as[t] / S + 1.0);
-                if (adam) {
-                    adam_update(loc[j], adam->m1_loc[j], adam->m2_loc[j], gl,
-                                adam->t, adam->lr, adam->b1, adam->b2, adam->eps);
-                    adam_update(logscale[j], adam->m1_ls[j], adam->m2_ls[j], gs,
-                                adam->t, adam->lr, adam->b1, adam->b2, adam->eps);
-                } else if (gloc) {
-                    gloc[j] = gl;
-                    glogscale[j] = gs;
-                }
-            }
+            for (int c = 0; c < 12; ++c)
+                if (c < NS) E[c] = 0.0 + src[c];
+            grad_sample(P, st, k, s, E, am, as, gz_out);
         }
     }
+    grad_finish(P, st, k, scale, scale_dev, gloc, glogscale, loc, logscale, adam, am, as);
 }
 
 }  // namespace xrdvi
