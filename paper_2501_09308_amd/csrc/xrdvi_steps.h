@@ -285,8 +285,9 @@ __device__ inline void grad_sample(const ProbDev &P, const StepDev &st, int k, i
     }
 }
 
-// One wave: sums am and as over its lanes; lane 0 stores the gradient of
-// phase k's 2 D parameters, or with `adam` updates loc / logscale in place.
+// One wave: sums am and as over its lanes (every lane receives the sums);
+// then lane t < D stores the gradient of phase k's loc of latent type t and
+// lane 32 + t that of its logscale, or with `adam` updates them in place.
 __device__ inline void grad_finish(const ProbDev &P, const StepDev &st, int k,
                                    double scale, const double *scale_dev,
                                    double *gloc, double *glogscale, double *loc,
@@ -299,24 +300,25 @@ __device__ inline void grad_finish(const ProbDev &P, const StepDev &st, int k,
         am[t] = wave_sum(am[t]);
         as[t] = wave_sum(as[t]);
     }
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-        if (scale_dev) scale *= *scale_dev;
+    const int lane = threadIdx.x & (kWave - 1), t = lane & 31;
+    const bool ls = lane >= 32;   // the logscale half of the wave
+    if (t >= NT) return;
+    double a = 0.0;
 #pragma unroll
-        for (int t = 0; t < 5; ++t) {
-            if (t >= NT) break;
-            const int j = t * K + k;
-            const double gl = scale * (am[t] / S);
-            const double gs = scale * (as[t] / S + 1.0);
-            if (adam) {
-                adam_update(loc[j], adam->m1_loc[j], adam->m2_loc[j], gl,
-                            adam->t, adam->lr, adam->b1, adam->b2, adam->eps);
-                adam_update(logscale[j], adam->m1_ls[j], adam->m2_ls[j], gs,
-                            adam->t, adam->lr, adam->b1, adam->b2, adam->eps);
-            } else if (gloc) {
-                gloc[j] = gl;
-                glogscale[j] = gs;
-            }
-        }
+    for (int u = 0; u < 5; ++u)
+        if (u == t) a = ls ? as[u] : am[u];
+    if (scale_dev) scale *= *scale_dev;
+    const int j = t * K + k;
+    const double g = ls ? scale * (a / S + 1.0) : scale * (a / S);
+    if (adam) {
+        if (ls)
+            adam_update(logscale[j], adam->m1_ls[j], adam->m2_ls[j], g,
+                        adam->t, adam->lr, adam->b1, adam->b2, adam->eps);
+        else
+            adam_update(loc[j], adam->m1_loc[j], adam->m2_loc[j], g,
+                        adam->t, adam->lr, adam->b1, adam->b2, adam->eps);
+    } else if (gloc) {
+        (ls ? glogscale : gloc)[j] = g;
     }
 }
 
