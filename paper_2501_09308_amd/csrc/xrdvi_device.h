@@ -1660,6 +1660,11 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
     const double mu = ph[K + k];
     const float iw2 = (float)(2.0 / ph[2 * K + k]);
     const float iw2r = ASYM ? asym_iw2(ph[2 * K + k], ph[4 * K + k]) : iw2;
+    // constant width: x - rho is formed already scaled by 2/w in FP64, so
+    // that q2 below the centre is one rounding of it (above the centre of an
+    // asymmetric peak it is that times 1/alpha)
+    const double iw2d = 2.0 / ph[2 * K + k];
+    const float up_ratio = ASYM ? (float)(1.0 / ph[4 * K + k]) : 1.f;
     // bounded buffer views of the residual (one per peak, below) and the
     // grid: 32-bit offsets, and reads past the end return 0
     const float *rres_s = st.rres + (size_t)s * P.N;
@@ -1710,19 +1715,24 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
         // x_i - rho = e + t in FP64.  On a uniform grid x_i is formed, not
         // loaded, so only the residuals are read: e is the lane's offset in
         // the first chunk, x0 + (lo + lane) dx - rho, and t the chunk's c dx;
-        // otherwise e = -rho and t = x_i, loaded
+        // otherwise e = -rho and t = x_i, loaded.  With a constant width e
+        // and t carry the factor 2/w (e by a multiply here, c dx by the
+        // chunk step, a loaded x_i by a fused multiply-add)
         double e[kAdjPeaks];
 #pragma unroll
         for (int q = 0; q < kAdjPeaks; ++q) {
             rq[q] = __builtin_amdgcn_make_buffer_rsrc(
                 (void *)(rres_s + lo[q]), (short)0, len[q] * 4, kBufferFlags);
             e[q] = unif ? fma((double)lo[q], P.dx, xl) - rho[q] : -rho[q];
+            if (!SEC) e[q] *= iw2d;
         }
         // the chunks of the peaks' windows, one loop per kind of grid
         auto chunks = [&](auto unif_tag) {
             constexpr bool UNIF = decltype(unif_tag)::value;
+            // the chunk's c dx (scaled by 2/w with a constant width)
+            const double step = SEC ? dxw : dxw * iw2d;
             double cdx = 0.0;
-            for (int c = 0; c < span; c += kWave, cdx += dxw) {
+            for (int c = 0; c < span; c += kWave, cdx += step) {
                 float R[kAdjPeaks], rv[kAdjPeaks], d[kAdjPeaks];
                 double xv[kAdjPeaks];
 #pragma unroll
@@ -1742,7 +1752,9 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
 #pragma unroll
                 for (int q = 0; q < kAdjPeaks; ++q) {
                     R[q] = rv[q] * I[q];
-                    d[q] = (float)(e[q] + (UNIF ? cdx : xv[q]));
+                    // sec law: x - rho; constant width: (x - rho) 2/w
+                    d[q] = (float)(SEC || UNIF ? e[q] + (UNIF ? cdx : xv[q])
+                                              : fma(xv[q], iw2d, e[q]));
                 }
                 AdjPt pt[kAdjPeaks];
                 SecW wl[kAdjPeaks], wh[kAdjPeaks];
@@ -1751,8 +1763,10 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
                 for (int q = 0; q < kAdjPeaks; ++q) {
                     wl[q] = SecW::of(SEC ? tw[q] : 0.f);
                     wh[q] = SecW::of(SEC ? tw[q] * ka : 0.f);
-                    pt[q] = adj_point_L<ASYM, SEC>(R[q], d[q], iw2 * cq[q], iw2r * cq[q],
-                                                   cq[q], wl[q], wh[q], acc);
+                    pt[q] = SEC ? adj_point_L<ASYM, SEC>(R[q], d[q], iw2 * cq[q], iw2r * cq[q],
+                                                         cq[q], wl[q], wh[q], acc)
+                                : adj_point_L<ASYM, SEC>(R[q], d[q], 1.f, up_ratio, 1.f,
+                                                         wl[q], wh[q], acc);
                     // (points outside the window lie beyond 8 FWHM: no effect)
                     gauss = gauss | (pt[q].tt <= kGaussTT);
                 }
