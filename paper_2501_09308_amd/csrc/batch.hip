@@ -181,7 +181,11 @@ __global__ __launch_bounds__(kBlock, WIN && !SEC ? 6 : 1) void kb_fused(const Sl
         if (s >= d.st.S) continue;
         // windowed: forward only (the adjoint is peak-major); dense: fused
         if constexpr (WIN) {
-            win_tile<ASYM, SEC>(d.P, d.st, t, s, nullptr, sm);
+            // records in grid steps on a uniform grid (constant width only)
+            if (!SEC && uses_grid_steps(d.P))
+                win_tile<ASYM, SEC, !SEC>(d.P, d.st, t, s, nullptr, sm);
+            else
+                win_tile<ASYM, SEC, false>(d.P, d.st, t, s, nullptr, sm);
         } else {
             fused_tile<false, true, ASYM, SEC>(d.P, d.st, t, s, nullptr, sm);
         }

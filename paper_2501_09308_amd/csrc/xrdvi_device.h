@@ -1323,7 +1323,11 @@ __device__ void win_phase_global(const SegPeaks &sp, int4 r, int2 r2,
 // One staged record's terms at the lane's points (lane and lane + 64 of
 // the tile).  Only the lanes whose point lies in the window take part: a
 // half tile the window misses is skipped by the whole wave.
-template <bool ASYM, bool GAUSS>
+// UNIF (a uniform grid): u holds the points' exact offsets from the
+// tile's reference point in grid steps, and the records hold the centre,
+// its rounding error and the scales in grid steps as well, so the points
+// carry no rounding error of their own.
+template <bool ASYM, bool GAUSS, bool UNIF>
 __device__ __forceinline__ void win_record(const WinRecord<ASYM> r,
                                            const float (&u)[kPPL],
                                            const float (&ul)[kPPL], int lane,
@@ -1335,10 +1339,15 @@ __device__ __forceinline__ void win_record(const WinRecord<ASYM> r,
         const bool in = (unsigned)(d0 + p * kWave) < (unsigned)len;
         if (GAUSS) {
             if (in) {
+                asm volatile("");   // a branch, as below
                 float q2;
                 if (ASYM) {
-                    const float d = (u[p] - r.c) + (ul[p] - r.cl);
+                    const float d = UNIF ? (u[p] - r.c) - r.cl
+                                         : (u[p] - r.c) + (ul[p] - r.cl);
                     q2 = d * (d >= 0.f ? ah : r.s);
+                } else if (UNIF) {
+                    // (u - centre) s - cl s, cl s kept in the record
+                    q2 = fmaf(u[p] - r.c, r.s, -r.cl);
                 } else {
                     // (u - centre) s + (ul s - cl s), cl s kept in the record
                     q2 = fmaf(u[p] - r.c, r.s, fmaf(ul[p], r.s, -r.cl));
@@ -1348,9 +1357,9 @@ __device__ __forceinline__ void win_record(const WinRecord<ASYM> r,
                 sig[p] = fmaf(r.aG, exp2_f32(-tt), sig[p]);
             }
         } else if (in) {
-            // (an empty volatile statement keeps this short body a branch,
-            // which the wave skips when the half misses the window; the
-            // compiler would otherwise evaluate it at both halves and select)
+            // (an empty volatile statement keeps a short body a branch, which
+            // the wave skips when the half misses the window; the compiler
+            // would otherwise evaluate it at both halves and select)
             asm volatile("");
             float q2;
             if (ASYM) {
@@ -1391,9 +1400,18 @@ __device__ __forceinline__ int2 xcd_sample_group(int S) {
     return make_int2(i / G, (b % kXcds) * G + i % G);
 }
 
-template <bool ASYM, bool SEC, typename SM>
+// Whether the windowed forward stages its records in grid steps: a uniform
+// grid of more than one point.
+__host__ __device__ inline bool uses_grid_steps(const ProbDev &P) {
+    return P.uniform != 0 && P.N > 1;
+}
+
+// UNIF (constant width, uniform grid): the staged records and the points
+// are in grid steps relative to the tile's reference point (see win_record).
+template <bool ASYM, bool SEC, bool UNIF, typename SM>
 __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
                          float *f_out, SM &sm) {
+    static_assert(!(UNIF && SEC), "grid-step records need a constant width");
     constexpr int kCap = SM::kCap;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -1408,7 +1426,8 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
     const float *psec = SEC ? reinterpret_cast<const float *>(st.psec + (size_t)s * P.T)
                             : nullptr;
     const double *ph = st.phi + (size_t)s * P.D * K;
-    const double xref = P.x[min(i0 + kTile / 2, P.N - 1)];   // the tile's reference
+    const int iref = min(i0 + kTile / 2, P.N - 1);
+    const double xref = P.x[iref];   // the tile's reference
     const int i1 = min(i0 + kTile, P.N);
     const double xa = P.x[i0], xb = P.x[i1 - 1];
     SegPeaks sp;
@@ -1419,7 +1438,7 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
     sp.whi = as_const(whi);
     sp.sec = as_const(psec);
 
-    float u[kPPL], ul[kPPL];
+    float u[kPPL], ul[kPPL], ug[kPPL];
     int idx[kPPL];
     float sig[kPPL];
 #pragma unroll
@@ -1427,8 +1446,11 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
         idx[p] = i0 + p * kWave + lane;
         u[p] = P.u[idx[p]];
         ul[p] = P.ul[idx[p]];
+        ug[p] = (float)(idx[p] - iref);   // exact
         sig[p] = 0.f;
     }
+    // grid steps per degree (uniform grid)
+    const double gpd = P.inv_dx;
 
     for (int c0 = 0; c0 < K; c0 += kWinChunk) {
         const int nk = min(kWinChunk, K - c0);
@@ -1483,11 +1505,15 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
                 const double pj = P.pos[j];
                 const float I = SEC ? psec[4 * j + 1] : P.inten[j];
                 const float c = SEC ? psec[4 * j] : 1.f;
-                float alo = iw2 * c, ahi = alo;
+                // (in grid steps the scales are 2 dx / w: the degree scales
+                // times dx)
+                const float iw2u = UNIF ? (float)((double)iw2 * P.dx) : iw2;
+                const float iw2ru = UNIF ? (float)((double)iw2r * P.dx) : iw2r;
+                float alo = iw2u * c, ahi = alo;
                 if (ASYM) {
                     // centre at or below the tile's first point: the tile
                     // lies above it; at or below its last: it straddles it
-                    const float ar = iw2r * c;
+                    const float ar = iw2ru * c;
                     const double rho = pj + pw.mu;
                     if (!(rho > xa)) alo = ahi = ar;
                     else if (!(rho > xb)) ahi = ar;
@@ -1496,7 +1522,8 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
                 const int slot = gauss ? exclg + (j - gr.x)
                                        : kCap - 1 - excln -
                                              (j < gr.x ? j - pw.ja : q - cg);
-                const double cx = (pj - xref) + pw.mu;
+                const double cxd = (pj - xref) + pw.mu;
+                const double cx = UNIF ? cxd * gpd : cxd;   // grid steps if UNIF
                 const float cxf = (float)cx;
                 // symmetric peaks keep the centre times the scale (records
                 // without the Gaussian) or the rounding error of the centre
@@ -1532,11 +1559,22 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
         n_fit = __builtin_amdgcn_readfirstlane(n_fit);
 
         // the waves share the two lists
-#pragma unroll 2
-        for (int f = wv; f < n_g; f += kWaves)
-            win_record<ASYM, true>(sm.rec[f], u, ul, lane, sig);
-        for (int f = wv; f < n_n; f += kWaves)   // (its body keeps a branch: not unrolled)
-            win_record<ASYM, false>(sm.rec[kCap - 1 - f], u, ul, lane, sig);
+        // (two records per pass, unrolled by hand: the volatile statements
+        // in the record bodies keep the compiler from unrolling)
+        const float (&uu)[kPPL] = UNIF ? ug : u;
+        int f = wv;
+        for (; f + kWaves < n_g; f += 2 * kWaves) {
+            const WinRecord<ASYM> r0 = sm.rec[f], r1 = sm.rec[f + kWaves];
+            win_record<ASYM, true, UNIF>(r0, uu, ul, lane, sig);
+            win_record<ASYM, true, UNIF>(r1, uu, ul, lane, sig);
+        }
+        if (f < n_g) win_record<ASYM, true, UNIF>(sm.rec[f], uu, ul, lane, sig);
+        for (f = wv; f + kWaves < n_n; f += 2 * kWaves) {
+            const WinRecord<ASYM> r0 = sm.rec[kCap - 1 - f], r1 = sm.rec[kCap - 1 - f - kWaves];
+            win_record<ASYM, false, UNIF>(r0, uu, ul, lane, sig);
+            win_record<ASYM, false, UNIF>(r1, uu, ul, lane, sig);
+        }
+        if (f < n_n) win_record<ASYM, false, UNIF>(sm.rec[kCap - 1 - f], uu, ul, lane, sig);
         // phases that did not fit (every lane finds the same ranges)
         for (int kl = n_fit + wv; kl < nk; kl += kWaves) {
             const int k = c0 + kl;

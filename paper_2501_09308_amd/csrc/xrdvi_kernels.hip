@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kWideWaves * kWave) void k_fused_wide(ProbDev P, St
 // register budget is held to the occupancy the staging space allows (seven
 // blocks per CU, six with asymmetric records; the sec-law variants are
 // left unbounded).
-template <bool ASYM, bool SEC>
+template <bool ASYM, bool SEC, bool UNIF>
 __global__ __launch_bounds__(kBlock, SEC ? 1 : (ASYM ? 6 : 7)) void k_win(ProbDev P, StepDev st,
                                                 float *f_out) {
     __shared__ WinSmem<ASYM> sm;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kBlock, SEC ? 1 : (ASYM ? 6 : 7)) void k_win(ProbDe
     const int2 ts = SEC ? make_int2(blockIdx.x, blockIdx.y)
                   : st.S % kXcds == 0 ? xcd_sample_group(st.S)
                                       : xcd_tile_sample(P.ntiles, st.S);
-    win_tile<ASYM, SEC>(P, st, ts.x, ts.y, f_out, sm);
+    win_tile<ASYM, SEC, UNIF>(P, st, ts.x, ts.y, f_out, sm);
 }
 
 // a6 (windowed): peak-major adjoint, one block per (sample, phase);
@@ -272,7 +272,11 @@ static void launch_fused_t(const ProbDev &P, const StepDev &st, bool grad,
     if (P.cutoff > 0.0) {
         StepDev sf = st;
         if (!grad) sf.rres = nullptr;
-        k_win<ASYM, SEC><<<g, kBlock, 0, stream>>>(P, sf, f_out);
+        // records in grid steps on a uniform grid (constant width only)
+        if (!SEC && uses_grid_steps(P))
+            k_win<ASYM, SEC, !SEC><<<g, kBlock, 0, stream>>>(P, sf, f_out);
+        else
+            k_win<ASYM, SEC, false><<<g, kBlock, 0, stream>>>(P, sf, f_out);
         if (grad) {
             dim3 ga(P.K, st.S);
             k_adjoint_win<ASYM, SEC><<<ga, kBlock, 0, stream>>>(P, st);
