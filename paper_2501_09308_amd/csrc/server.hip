@@ -151,7 +151,15 @@ class GpuExecutor : public Executor {
         // changes its shape and therefore its work units
         std::vector<std::pair<int, uint64_t>> members;
         for (const Job *j : active) members.emplace_back(j->slot, j->ticket);
-        std::sort(members.begin(), members.end());
+        // analyses with more peaks per point first: their work units are the
+        // larger ones, and the persistent grids deal units in this order,
+        // so the steps end on small units (then by slot, so the order is a
+        // function of the membership)
+        std::sort(members.begin(), members.end(), [&](const auto &l, const auto &r) {
+            const ProbDev &a = h_tab_[l.first].P, &b = h_tab_[r.first].P;
+            const double da = (double)a.T / a.N, db = (double)b.T / b.N;
+            return da != db ? da > db : l < r;
+        });
         // each variant's kernels run only while an analysis of it is resident
         unsigned classes = 0;
         for (const auto &m : members) classes |= 1u << batch_class(h_tab_[m.first].P);
