@@ -1227,7 +1227,8 @@ constexpr int kWinRecBytes = 21 * 1024;
 
 // A staged record.  Its FP32 centre relative to the tile is rounded;
 // records whose Gaussian reaches the tile also carry that rounding error cl
-// (x - rho is then formed as (u - centre) + (ul - cl), see PhasePts).
+// (x - rho is then formed as (u - centre) + (ul - cl), or on a uniform grid
+// in grid steps as (u - centre) - cl with u exact, see win_record).
 // Symmetric records keep the centre times the scale below (without the
 // Gaussian) or cl times that scale (with it), so that q2 takes fused
 // multiply-adds (see win_record).  The window is kept relative to the
