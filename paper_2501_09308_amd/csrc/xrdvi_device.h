@@ -1723,15 +1723,17 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
     float acc[NS];
 #pragma unroll
     for (int c = 0; c < NS; ++c) acc[c] = 0.f;
-    // wave wv takes peaks a + wv + kWaves * (kAdjPeaks * g + q), q < kAdjPeaks
-    for (int j0 = a + wv; j0 < b; j0 += kWaves * kAdjPeaks) {
+    // the phase's peaks in groups of kAdjPeaks consecutive ones (neighbours
+    // in position, with windows of one length), group g to wave g mod 4: only
+    // the phase's last group can be short
+    for (int j0 = a + kAdjPeaks * wv; j0 < b; j0 += kWaves * kAdjPeaks) {
         int lo[kAdjPeaks], len[kAdjPeaks];
         float I[kAdjPeaks], cq[kAdjPeaks], tw[kAdjPeaks];
         double rho[kAdjPeaks];
         int span = 0;
 #pragma unroll
         for (int q = 0; q < kAdjPeaks; ++q) {
-            const int j = j0 + kWaves * q;
+            const int j = j0 + q;
             const bool ok = j < b;
             const int jj = ok ? j : j0;
             lo[q] = wlo[jj];
