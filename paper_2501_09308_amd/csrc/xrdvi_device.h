@@ -1222,7 +1222,8 @@ constexpr int kWinChunk = kBlock;   // phases staged at a time (one per thread)
 // global-memory path, and so the order in which a point's terms are summed,
 // depends on it, and a served analysis gives the same bits as its
 // one-at-a-time run only if both kernels stage alike.  21 KB hold 896
-// symmetric or 672 asymmetric records (seven blocks per CU).
+// symmetric or 672 asymmetric records (seven blocks per CU; the asymmetric
+// forward's registers hold it to six).
 constexpr int kWinRecBytes = 21 * 1024;
 
 // A staged record.  Its FP32 centre relative to the tile is rounded;
