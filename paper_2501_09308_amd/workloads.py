@@ -20,8 +20,9 @@ from typing import Optional
 
 import numpy as np
 
-# Named workloads.  Sizes follow the configurations the hot path is
-# measured on; see the design doc for the recipe.
+# Named workloads: the grid, candidate count, peaks per candidate, true
+# phases, samples per step and window cutoff of each configuration the hot
+# path is measured on.
 WORKLOADS = {
     # tiny: one sample, dense, 8 candidates x 20 peaks
     "tiny": dict(x0=10.0, step=0.02, N=3501, K=8, M=20, n_true=2, S=1,
