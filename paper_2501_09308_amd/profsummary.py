@@ -79,7 +79,7 @@ def short(name: str) -> str:
 
 def summarize(out, title, cmd, stats_csv, fetch=None, write=None, cfetch=None,
               cwrite=None, sq=None, flops=None, record_kernel=None, extra=""):
-    L = [f"# {title}", "", "Commands (run from the repository root on the GPU box):",
+    L = [f"# {title}", "", "Commands (run from the repository root on an MI355X):",
          "", "```", cmd, "```", "",
          "| kernel | calls | avg us | min us | max us | % time |",
          "|---|---|---|---|---|---|"]
