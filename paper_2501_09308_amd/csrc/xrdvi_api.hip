@@ -201,6 +201,7 @@ hipError_t upload_problem(const xrdvi_problem_desc &d, double lambda,
             P.uniform = 0;
             break;
         }
+    P.formed_x = P.uniform && (P.sec || P.D == 5 || P.cutoff <= kF32Cutoff) ? 1 : 0;
     P.lambda = lambda;
     P.mu_sd = d.prior.mu_sd;
     P.w_shape = d.prior.w_shape;

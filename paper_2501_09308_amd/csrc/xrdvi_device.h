@@ -76,8 +76,13 @@ struct ProbDev {
                                       // (0 for N = 1): grid-search guesses
     double dx;                        // (x[N-1] - x[0]) / (N - 1) (0 for N = 1)
     int uniform;                      // 1: every x_i lies within 1e-9 dx of
-                                      // x0 + i dx (the windowed adjoint then
-                                      // forms x_i instead of loading it)
+                                      // x0 + i dx
+    int formed_x;                     // 1: the windowed adjoint forms x_i
+                                      // instead of loading it (a uniform
+                                      // grid; symmetric peaks of constant
+                                      // width, whose q2 it then forms in
+                                      // FP32, only with windows of at most
+                                      // kF32Cutoff FWHM)
     const float *u;                   // [ntiles * kTile] x_i - xref_tile
                                       // (FP32, rounded)
     const float *ul;                  // [ntiles * kTile] its rounding
@@ -1596,10 +1601,12 @@ __device__ void win_tile(const ProbDev &P, const StepDev &st, int t, int s,
 
 // ---- peak-major adjoint (windowed mode) -----------------------------------
 //
-// One block of kWaves waves per (sample s, phase k); wave w takes peaks
-// a + w, a + w + kWaves, ...  For every peak the lanes cover consecutive
-// points of its window (64 at a time); x - rho is formed in FP64 and
-// rounded to FP32 (its sign picks the side of an asymmetric peak).  Six
+// One block of kWaves waves per (sample s, phase k); the phase's peaks go
+// in groups of kAdjPeaks consecutive ones, group g to wave g mod kWaves.
+// For every peak the lanes cover consecutive points of its window (64 at a
+// time); x - rho is formed in FP64 and rounded to FP32 (its sign picks the
+// side of an asymmetric peak), or for symmetric peaks of constant width on
+// a uniform grid from FP32 offsets each rounded once (adjoint_phase).  Six
 // sums (twelve: six per side) accumulate per lane over the wave's peaks,
 // are reduced over the wave, then over the waves in fixed order.
 // R = 0 for lanes outside the window (their terms vanish).  SEC: iw2 and
@@ -1689,6 +1696,14 @@ constexpr int kBufferFlags = 0x00020000;
 // back to back, so one memory latency covers all of them.
 constexpr int kAdjPeaks = 4;
 
+// Windows of at most this many FWHM each side (symmetric peaks of constant
+// width on a uniform grid): the adjoint forms q2 = 2 (x - rho) / w in FP32.
+// |q2| is at most 2c inside a window and its chunk offsets at most 4c, so
+// each of its three roundings errs by at most 4c 2^-24: q2 is exact to
+// 12c 2^-24, about 6e-6 at c = 8 and 1.1e-5 at this bound (a relative
+// gradient error of that order, against a bar of 1e-4).
+constexpr double kF32Cutoff = 16.0;
+
 template <bool ASYM, bool SEC>
 __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
                                      int s, int k, double (*red)[12]) {
@@ -1702,7 +1717,8 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
     const float iw2r = ASYM ? asym_iw2(ph[2 * K + k], ph[4 * K + k]) : iw2;
     // constant width: x - rho is formed already scaled by 2/w in FP64, so
     // that q2 below the centre is one rounding of it (above the centre of an
-    // asymmetric peak it is that times 1/alpha)
+    // asymmetric peak it is that times 1/alpha); symmetric peaks on a uniform
+    // grid take FP32 from there (the chunk loop)
     const double iw2d = 2.0 / ph[2 * K + k];
     const float up_ratio = ASYM ? (float)(1.0 / ph[4 * K + k]) : 1.f;
     // bounded buffer views of the residual (one per peak, below) and the
@@ -1717,7 +1733,7 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
     cptr<float> psec = SEC ? as_const(reinterpret_cast<const float *>(st.psec + (size_t)s * P.T))
                            : nullptr;
     const float ka = ASYM ? (float)ph[4 * K + k] : 1.f;
-    const bool unif = P.uniform != 0;
+    const bool unif = P.formed_x != 0;
     const double xl = fma((double)lane, P.dx, P.x0);   // uniform grid: x0 + lane dx
     const double dxw = kWave * P.dx;                     // one chunk of points
     const int a = P.off[k], b = P.off[k + 1];
@@ -1771,10 +1787,21 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
         // the chunks of the peaks' windows, one loop per kind of grid
         auto chunks = [&](auto unif_tag) {
             constexpr bool UNIF = decltype(unif_tag)::value;
+            // symmetric peaks of constant width on a uniform grid: q2 is
+            // formed in FP32 as the chunk's index times the chunk step plus
+            // the lane's offset, each rounded once (one fused multiply-add
+            // per point instead of an FP64 sum and a conversion; no side of
+            // a peak depends on its sign)
+            constexpr bool F32 = UNIF && !SEC && !ASYM;
             // the chunk's c dx (scaled by 2/w with a constant width)
             const double step = SEC ? dxw : dxw * iw2d;
+            const float stepf = (float)step;
+            float ef[kAdjPeaks];
+#pragma unroll
+            for (int q = 0; q < kAdjPeaks; ++q) ef[q] = (float)e[q];
             double cdx = 0.0;
-            for (int c = 0; c < span; c += kWave, cdx += step) {
+            float cf = 0.f;
+            for (int c = 0; c < span; c += kWave, cdx += step, cf += 1.f) {
                 float R[kAdjPeaks], rv[kAdjPeaks], d[kAdjPeaks];
                 double xv[kAdjPeaks];
 #pragma unroll
@@ -1795,8 +1822,9 @@ __device__ inline void adjoint_phase(const ProbDev &P, const StepDev &st,
                 for (int q = 0; q < kAdjPeaks; ++q) {
                     R[q] = rv[q] * I[q];
                     // sec law: x - rho; constant width: (x - rho) 2/w
-                    d[q] = (float)(SEC || UNIF ? e[q] + (UNIF ? cdx : xv[q])
-                                              : fma(xv[q], iw2d, e[q]));
+                    d[q] = F32 ? fmaf(cf, stepf, ef[q])
+                               : (float)(SEC || UNIF ? e[q] + (UNIF ? cdx : xv[q])
+                                                     : fma(xv[q], iw2d, e[q]));
                 }
                 AdjPt pt[kAdjPeaks];
                 SecW wl[kAdjPeaks], wh[kAdjPeaks];

@@ -82,6 +82,12 @@ ELBO_CASES = [
     ("paper50", 204, dict(N=1000), 5, 0.0),
     ("stress200", 205, dict(K=300, M=20, N=3001), 4, 8.0),
     ("stress200", 206, dict(K=260, M=100, N=600), 3, 8.0),
+    # the adjoint's FP32 offsets (symmetric peaks, constant width, uniform
+    # grid) at the widest windows that take them, and the loaded-grid path
+    # of wider windows, up to windows wider than the grid
+    ("paper50", 207, dict(N=1500), 4, 16.0),
+    ("paper50", 208, dict(N=1500), 4, 30.0),
+    ("paper50", 209, dict(N=1500), 2, 1e6),
 ]
 
 
