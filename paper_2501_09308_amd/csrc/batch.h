@@ -14,7 +14,7 @@ constexpr int kMaxSlots = 512;
 // (windowed or dense, symmetric or asymmetric peaks, constant or sec-law
 // width), so that each kernel keeps the register budget of its
 // single-analysis counterpart.
-enum BatchKind { kSample = 0, kWindows, kWindowsSec, kPlan, kPlanSec, kCandExt, kCand,
+enum BatchKind { kSample = 0, kWindows, kWindowsSec, kPlan, kPlanSec, kCand,
                  kFusedWin, kFusedDense, kFusedWinAsym, kFusedDenseAsym,
                  kFusedWinSec, kFusedDenseSec, kFusedWinAsymSec,
                  kFusedDenseAsymSec,
@@ -65,7 +65,9 @@ inline void batch_units(const ProbDev &P, int S, int units[kKinds]) {
     if (!win)   // the windowed forward tile finds its own ranges
         units[sec ? kPlanSec : kPlan] = (int)(((long long)S * P.ntiles * P.K + 255) / 256);
     if (win && !sec) {   // ... among candidates found once per step
-        units[kCandExt] = (P.K + kWave - 1) / kWave;
+        // the phases' extremes over the samples, 64 phases per unit, run as
+        // the window step's first units
+        units[kWindows] += (int)nkb;
         units[kCand] = (int)(((long long)P.K + kCandThreads - 1) / kCandThreads) * P.ntiles;
     }
     units[fused_kind(win, asym, sec)] = P.ntiles * S;

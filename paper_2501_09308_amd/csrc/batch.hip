@@ -87,17 +87,31 @@ __global__ __launch_bounds__(256) void kb_sample(const SlotDev *tab,
     }
 }
 
+// The window step.  With a constant width (windowed analyses) an
+// analysis's first ceil(K / 64) units find its phases' extremes over the
+// samples instead, 64 phases each (see batch_units).
 template <bool SEC>
 __global__ __launch_bounds__(256) void kb_windows(const SlotDev *tab,
                                                   const SchedDev *sch) {
     __shared__ PrefixSmem ps;
+    __shared__ typename std::conditional<SEC, char, CandExtSmem>::type sm;
     load_prefix(sch, SEC ? kWindowsSec : kWindows, ps);
     const int total = uniform(ps.pre[ps.n]);
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         const int i = find_slot(ps, u);
         const SlotDev &d = slot_entry(tab, ps, i);
         if (!running(d)) continue;
-        const size_t g = (size_t)local_unit(ps, i, u) * 256 + threadIdx.x;
+        int local = local_unit(ps, i, u);
+        if constexpr (!SEC) {
+            const int next = (d.P.K + kWave - 1) / kWave;
+            if (local < next) {
+                if (d.st.cab) cand_ext_block(d.P, d.st, d.st.phi, local * kWave, sm);
+                __syncthreads();   // the extremes' LDS is reused by the next unit
+                continue;
+            }
+            local -= next;
+        }
+        const size_t g = (size_t)local * 256 + threadIdx.x;
         if (g < (size_t)d.st.S * d.P.T)
             windows_elem<SEC>(d.P, d.st.phi, d.P.cutoff > 0.0 ? d.st.lo : nullptr,
                               d.st.hi, nullptr, g, d.st.psec);
@@ -116,21 +130,6 @@ __global__ __launch_bounds__(256) void kb_plan(const SlotDev *tab,
         if (!running(d)) continue;
         const size_t g = (size_t)local_unit(ps, i, u) * 256 + threadIdx.x;
         if (g < (size_t)d.st.S * d.P.ntiles * d.P.K) plan_elem<SEC>(d.P, d.st, d.st.phi, g);
-    }
-}
-
-__global__ __launch_bounds__(kCandThreads) void kb_cand_ext(const SlotDev *tab,
-                                                            const SchedDev *sch) {
-    __shared__ PrefixSmem ps;
-    __shared__ CandExtSmem sm;
-    load_prefix(sch, kCandExt, ps);
-    const int total = uniform(ps.pre[ps.n]);
-    for (int u = blockIdx.x; u < total; u += gridDim.x) {
-        const int i = find_slot(ps, u);
-        const SlotDev &d = slot_entry(tab, ps, i);
-        if (!running(d) || !d.st.cab) continue;
-        cand_ext_block(d.P, d.st, d.st.phi, local_unit(ps, i, u) * kWave, sm);
-        __syncthreads();
     }
 }
 
@@ -286,10 +285,7 @@ hipError_t launch_batch_step(const SlotDev *tab, const SchedDev *sch,
     if (any(-1, 1)) kb_windows<true><<<kGridLarge, 256, 0, s>>>(tab, sch);
     if (any(0, 0)) kb_plan<false><<<kGridLarge, 256, 0, s>>>(tab, sch);
     if (any(0, 1)) kb_plan<true><<<kGridLarge, 256, 0, s>>>(tab, sch);
-    if (any(1, 0)) {
-        kb_cand_ext<<<kGridSmall, kCandThreads, 0, s>>>(tab, sch);
-        kb_cand<<<kGridLarge, kCandThreads, 0, s>>>(tab, sch);
-    }
+    if (any(1, 0)) kb_cand<<<kGridLarge, kCandThreads, 0, s>>>(tab, sch);
     if (has(true, false, false)) kb_fused<true, false, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
     if (has(false, false, false)) kb_fused<false, false, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);
     if (has(true, true, false)) kb_fused<true, true, false><<<kGridLarge, kBlock, 0, s>>>(tab, sch);

@@ -86,14 +86,26 @@ __global__ void k_plan(ProbDev P, StepDev st, const double *__restrict__ phi) {
         plan_elem<SEC>(P, st, phi, g);
 }
 
-// a2 (windowed, constant width): the phases' extremes over the samples,
-// grid ceil(K / 64); then the candidate ranges, grid (ceil(K / 256),
-// ntiles), one thread per (tile, phase).
-__global__ __launch_bounds__(kCandThreads) void k_cand_ext(ProbDev P, StepDev st,
-                                                           const double *__restrict__ phi) {
+// a2 (windowed, constant width): the window step and the phases' extremes
+// over the samples in one launch.  Blocks [0, next) take 64 phases each,
+// the others one thread per (sample, peak) as k_windows.
+__global__ __launch_bounds__(kCandThreads) void k_windows_ext(ProbDev P, StepDev st,
+                                                              const double *__restrict__ phi,
+                                                              int next) {
     __shared__ CandExtSmem sm;
-    cand_ext_block(P, st, phi, blockIdx.x * kWave, sm);
+    if ((int)blockIdx.x < next) {
+        cand_ext_block(P, st, phi, blockIdx.x * kWave, sm);
+        return;
+    }
+    const size_t n = (size_t)st.S * P.T;
+    const size_t nb = gridDim.x - next;
+    for (size_t g = (size_t)(blockIdx.x - next) * blockDim.x + threadIdx.x; g < n;
+         g += nb * blockDim.x)
+        windows_elem<false>(P, phi, st.lo, st.hi, nullptr, g, nullptr);
 }
+
+// The candidate ranges, grid (ceil(K / 256), ntiles), one thread per
+// (tile, phase).
 __global__ __launch_bounds__(kCandThreads) void k_cand(ProbDev P, StepDev st) {
     const int k = blockIdx.x * kCandThreads + threadIdx.x;
     if (k < P.K) cand_elem(P, st, blockIdx.y, k);
@@ -235,21 +247,32 @@ hipError_t launch_windows(const ProbDev &P, int S, const double *phi, int *lo,
     return hipGetLastError();
 }
 
+// The window step.  Windowed with a constant width it also finds the
+// phases' extremes over the samples (for launch_plan, which follows it).
 hipError_t launch_peak_plan(const ProbDev &P, const StepDev &st,
                             const double *phi, hipStream_t stream) {
     if (P.cutoff == 0.0 && !P.sec) return hipSuccess;
+    if (P.cutoff > 0.0 && !P.sec && st.cab) {
+        const int next = (P.K + kWave - 1) / kWave;
+        size_t blocks = ((size_t)st.S * P.T + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        if (blocks == 0) blocks = 1;
+        k_windows_ext<<<(unsigned)(next + blocks), kCandThreads, 0, stream>>>(P, st, phi,
+                                                                              next);
+        return hipGetLastError();
+    }
     return launch_windows(P, st.S, phi, P.cutoff > 0.0 ? st.lo : nullptr,
                           st.hi, nullptr, stream, P.sec ? st.psec : nullptr);
 }
 
 // Dense mode: the tile plan.  Windowed mode with a constant width: the
-// candidate ranges of each (tile, phase) over the step's samples (the
-// windowed forward tile then finds its exact ranges among them).
+// candidate ranges of each (tile, phase) over the step's samples, from the
+// phases' extremes that launch_peak_plan found (the windowed forward tile
+// then finds its exact ranges among them).
 hipError_t launch_plan(const ProbDev &P, const StepDev &st, const double *phi,
                        hipStream_t stream) {
     if (P.cutoff > 0.0) {
         if (!P.sec && st.cab) {
-            k_cand_ext<<<(P.K + kWave - 1) / kWave, kCandThreads, 0, stream>>>(P, st, phi);
             dim3 g((P.K + kCandThreads - 1) / kCandThreads, P.ntiles);
             k_cand<<<g, kCandThreads, 0, stream>>>(P, st);
         }
